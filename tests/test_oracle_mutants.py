@@ -1,0 +1,53 @@
+"""The pins must discriminate: each plausible mistake planted in a copy of the
+oracle source (one substitution, compiled to a scratch library on the CPU)
+must make at least one pin test fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "mfc_oracle.c")
+PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_units.py", "test_oracle_scheme.py")]
+
+MUTANTS = {
+    "weno ideal weights swapped": ("dplus[3] = {0.1, 0.6, 0.3}", "dplus[3] = {0.3, 0.6, 0.1}"),
+    "weno power 1 instead of 2": ("double den = (eps + beta[r]) * (eps + beta[r]);", "double den = (eps + beta[r]);"),
+    "weno beta0 coefficient": ("(10.0 / 3.0) * dm1 * dm1 - (11.0 / 3.0) * dm1 * dm2", "(10.0 / 3.0) * dm1 * dm1 - (10.0 / 3.0) * dm1 * dm2"),
+    "weno candidate coefficient": ("pp[1] = vi + (1.0 / 3.0) * d0", "pp[1] = vi + (1.0 / 6.0) * d0"),
+    "weno mirror candidate": ("pm[2] = vi - (5.0 / 6.0) * d0 + (1.0 / 3.0) * d1", "pm[2] = vi - (5.0 / 6.0) * d0 + (1.0 / 6.0) * d1"),
+    "hllc s* sign": ("double sS = (pR - pL + rhoL", "double sS = (pL - pR + rhoL"),
+    "hllc Davis min": ("double sL = fmin(uL - cL, uR - cR);", "double sL = uL - cL;"),
+    "hllc star energy term": ("(rho * sS + p / (sK - un))", "(rho * sS)"),
+    "hllc star normal momentum": ("(m == dir ? rho * sS : rho * w[2 + m])", "(rho * w[2 + m])"),
+    "hllc face alpha": ("alpha_face = w[nv - 1];", "alpha_face = wL[nv - 1];"),
+    "hllc pressure on every momentum row": ("(m == dir ? p : 0.0)", "p"),
+    "rhs no alpha div(u) source": ("+= w[at(g, nv - 1, i, j, k)] * divu", "+= 0.0 * divu"),
+    "rhs source sign": ("+= w[at(g, nv - 1, i, j, k)] * divu", "-= w[at(g, nv - 1, i, j, k)] * divu"),
+    "rhs flux difference sign": ("(Ff[cell * nv + v] - Ff[(cell + 1) * nv + v]) * inv_dx", "(Ff[(cell + 1) * nv + v] - Ff[cell * nv + v]) * inv_dx"),
+    "eos Pi without gamma": ("double h1 = g->gamma[0] * g->pi_inf[0]", "double h1 = g->pi_inf[0]"),
+    "eos kinetic factor": ("ke += 0.5 * q[2 + m] * w[2 + m];", "ke += q[2 + m] * w[2 + m];"),
+    "sound speed Gamma+1": ("return ((Gamma + 1.0) * p + Pi) / (Gamma * rho);", "return (Gamma * p + Pi) / (Gamma * rho);"),
+    "rk3 stage-2 weights": ("0.75 * q0[t] + 0.25 * (qs[t]", "0.25 * q0[t] + 0.75 * (qs[t]"),
+    "periodic ghost offset": ("int slo = g->bc[2 * d] == 1 ? n - l : 0;", "int slo = g->bc[2 * d] == 1 ? n - l + 1 : 0;"),
+    "extrapolation ghost": ("int shi = g->bc[2 * d + 1] == 1 ? l - 1 : n - 1;", "int shi = g->bc[2 * d + 1] == 1 ? l - 1 : n - l;"),
+    "cfl max over |u| only": ("double sd = fabs(wc[2 + d]) + c;", "double sd = fabs(wc[2 + d]);"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not found exactly once: {old!r}"
+    mutant_c = tmp_path / "mutant.c"
+    mutant_c.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared", "-o", str(so), str(mutant_c), "-lm"],
+                   check=True)
+    env = dict(os.environ, MFC_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"no pin failed for mutant '{name}':\n{r.stdout[-2000:]}"
