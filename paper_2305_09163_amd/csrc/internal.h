@@ -1,0 +1,59 @@
+// Internal declarations shared by the library's translation units: the grid
+// handle, kernel launchers and status helpers.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mfc.h"
+#include "physics.h"
+
+struct mfc_grid {
+    mfc_grid_desc desc;
+    mfc::Grid g;           // device-side geometry/material constants
+    int nvar;
+    int64_t cells_padded;  // px * py * pz
+    int64_t cells;         // interior cells
+    int device;
+
+    // scratch owned by the handle (device memory)
+    void *stage_a = nullptr;   // RK stage state q^(1)
+    void *stage_b = nullptr;   // RK stage state q^(2)
+    double *prim = nullptr;    // staged path: primitive state (padded layout)
+    double *recp = nullptr;    // staged path: reconstruction at x_{i+1/2}, per cell
+    double *recm = nullptr;    // staged path: reconstruction at x_{i-1/2}, per cell
+    double *faces = nullptr;   // staged path: 3 directions x (nvar + 1) face arrays
+    double *partial = nullptr; // per-block maxima of the wave-speed reduction
+    double *scalars = nullptr; // [0] smax, [1] dt, [2] t, [3] spare
+    int *flag = nullptr;       // non-physical flag
+
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    size_t ev_used = 0;
+};
+
+namespace mfc {
+
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+
+// status helpers
+int fail(int status, const std::string &detail);
+int hip_status(hipError_t e, const char *what);
+
+// kernel timing: bracket one launch of the dominant kernel
+void timing_begin(mfc_grid *h, hipStream_t s);
+void timing_end(mfc_grid *h, hipStream_t s);
+
+// Launchers.  `q` has ghosts filled.  mode 0: out = rhs; mode s = 1, 2, 3:
+// out = a_s q0 + b_s (q + dt rhs) with the SSP-RK3 stage coefficients.
+// dt is *dt_dev if dt_dev is non-null, else dt.
+int launch_rhs_staged(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+                      const double *dt_dev, hipStream_t s);
+int launch_rhs_fused(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+                     const double *dt_dev, hipStream_t s);
+
+}  // namespace mfc

@@ -1,0 +1,571 @@
+// C ABI of the library (declared in include/mfc.h): argument validation,
+// scratch ownership, the small kernels around the right-hand side (ghost
+// fill, EOS conversions, the CFL reduction, the time-step bookkeeping) and
+// the SSP-RK3 driver.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace mfc {
+
+static thread_local char g_detail[512] = "";
+
+int fail(int status, const std::string &detail)
+{
+    std::snprintf(g_detail, sizeof g_detail, "%s", detail.c_str());
+    return status;
+}
+
+int hip_status(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return MFC_OK;
+    return fail(e == hipErrorOutOfMemory ? MFC_E_NOMEM : MFC_E_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void timing_begin(mfc_grid *h, hipStream_t s)
+{
+    if (!h->timing) return;
+    if (h->ev_used + 2 > h->ev.size()) {
+        for (int t = 0; t < 64; t++) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            h->ev.push_back(e);
+        }
+    }
+    (void)hipEventRecord(h->ev[h->ev_used], s);
+}
+
+void timing_end(mfc_grid *h, hipStream_t s)
+{
+    if (!h->timing || h->ev_used + 2 > h->ev.size()) return;
+    (void)hipEventRecord(h->ev[h->ev_used + 1], s);
+    h->ev_used += 2;
+}
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+// ------------------------------------------------------------ ghost fill
+// One thread per (variable, ghost layer, side, face-slab cell) of dimension d.
+__global__ void __launch_bounds__(kThreads) k_ghosts(Grid g, double *__restrict__ q, int nv, int d, int bc_lo,
+                                                     int bc_hi)
+{
+    int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+    int n1 = g.n[o1], n2 = g.n[o2], n = g.n[d];
+    int64_t per_var = (int64_t)2 * NG * n1 * n2;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= per_var * nv) return;
+    int v = (int)(t / per_var);
+    int64_t r = t % per_var;
+    int a = (int)(r % n1);
+    r /= n1;
+    int b = (int)(r % n2);
+    r /= n2;
+    int l = 1 + (int)(r % NG);
+    int side = (int)(r / NG);
+    int c[3], src[3];
+    c[o1] = src[o1] = a;
+    c[o2] = src[o2] = b;
+    if (side == 0) {
+        c[d] = -l;
+        src[d] = bc_lo == MFC_BC_PERIODIC ? n - l : 0;
+    } else {
+        c[d] = n - 1 + l;
+        src[d] = bc_hi == MFC_BC_PERIODIC ? l - 1 : n - 1;
+    }
+    auto off = [&](const int *x) {
+        return (int64_t)(x[2] + g.off[2]) * g.stride[2] + (int64_t)(x[1] + g.off[1]) * g.stride[1] + (x[0] + g.off[0]);
+    };
+    q[v * g.vstride + off(c)] = q[v * g.vstride + off(src)];
+}
+
+// ------------------------------------------------------ EOS conversions
+template <int NDIM>
+__global__ void __launch_bounds__(kThreads) k_p2c(Grid g, const double *__restrict__ w, double *__restrict__ q)
+{
+    constexpr int NV = 4 + NDIM;
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.vstride) return;
+    double wc[NV], qc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) wc[v] = w[v * g.vstride + c];
+    prim_to_cons<NDIM>(g, wc, qc);
+#pragma unroll
+    for (int v = 0; v < NV; v++) q[v * g.vstride + c] = qc[v];
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(kThreads) k_c2p(Grid g, const double *__restrict__ q, double *__restrict__ w,
+                                                  int *__restrict__ flag)
+{
+    constexpr int NV = 4 + NDIM;
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.vstride) return;
+    double qc[NV], wc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
+    if (cons_to_prim<NDIM>(g, qc, wc)) atomicOr(flag, 1);
+#pragma unroll
+    for (int v = 0; v < NV; v++) w[v * g.vstride + c] = wc[v];
+}
+
+// -------------------------------------------------- CFL wave-speed reduction
+// Per-block maxima of max_d (|u_d| + c) over interior cells (grid-stride),
+// reduced within each wavefront by butterfly shuffles and across the block
+// through LDS.  Maxima are exact and order-independent.
+template <int NDIM>
+__global__ void __launch_bounds__(kReduceThreads) k_wavespeed(Grid g, const double *__restrict__ q,
+                                                              double *__restrict__ partial, int *__restrict__ flag)
+{
+    constexpr int NV = 4 + NDIM, E = 2 + NDIM, A = 3 + NDIM;
+    __shared__ double red[kReduceThreads / 64];
+    double smax = 0.0;
+    const int64_t total = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    bool bad = false;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(t % g.n[0]);
+        int64_t r = t / g.n[0];
+        int j = (int)(r % g.n[1]);
+        int k = (int)(r / g.n[1]);
+        int64_t c = (int64_t)(k + g.off[2]) * g.stride[2] + (int64_t)(j + g.off[1]) * g.stride[1] + (i + g.off[0]);
+        double qc[NV], wc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
+        bad |= cons_to_prim<NDIM>(g, qc, wc);
+        double Gam, Pi;
+        mixture(g, wc[A], Gam, Pi);
+        double cs = __builtin_sqrt(sound2(Gam, Pi, wc[0] + wc[1], wc[E]));
+#pragma unroll
+        for (int d = 0; d < NDIM; d++) smax = __builtin_fmax(smax, __builtin_fabs(wc[2 + d]) + cs);
+    }
+    if (bad) atomicOr(flag, 2);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) smax = __builtin_fmax(smax, __shfl_xor(smax, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = smax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kReduceThreads / 64; w++) m = __builtin_fmax(m, red[w]);
+        partial[blockIdx.x] = m;
+    }
+}
+
+// One block: reduce the partial maxima, then set the step size and advance
+// the accumulated time.  scalars = [smax, dt, t].
+__global__ void __launch_bounds__(kReduceThreads) k_step_begin(const double *__restrict__ partial, int nblocks,
+                                                               double cfl, double dt_fixed, double dxmin,
+                                                               double *__restrict__ scalars)
+{
+    __shared__ double red[kReduceThreads / 64];
+    double m = 0.0;
+    if (partial)
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) m = __builtin_fmax(m, partial[b]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = __builtin_fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = red[0];
+        for (int w = 1; w < kReduceThreads / 64; w++) s = __builtin_fmax(s, red[w]);
+        double dt = dt_fixed;
+        if (partial) {
+            scalars[0] = s;
+            if (cfl > 0.0) dt = cfl * dxmin / s;
+        }
+        scalars[1] = dt;
+        scalars[2] += dt;
+    }
+}
+
+__global__ void k_set_scalars(double *scalars, int *flag, int what)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (what & 1) {
+            scalars[0] = scalars[1] = scalars[2] = scalars[3] = 0.0;
+        }
+        if (what & 2) *flag = 0;
+    }
+}
+
+// ---------------------------------------------------------------- helpers
+int validate(const mfc_grid_desc *d)
+{
+    if (!d) return fail(MFC_E_ARG, "desc is NULL");
+    if (d->ndim < 1 || d->ndim > 3) return fail(MFC_E_ARG, "ndim must be 1, 2 or 3");
+    if (d->num_fluids != 2) return fail(MFC_E_UNSUPPORTED, "num_fluids must be 2");
+    for (int k = 0; k < d->ndim; k++) {
+        if (d->n[k] < 3) return fail(MFC_E_ARG, "n must be >= 3 on active dimensions");
+        if (d->n[k] > (1 << 20)) return fail(MFC_E_ARG, "n too large");
+        if (!(d->hi[k] > d->lo[k]) || !std::isfinite(d->hi[k] - d->lo[k])) return fail(MFC_E_ARG, "hi must exceed lo");
+        int a = d->bc[2 * k], b = d->bc[2 * k + 1];
+        if ((a != MFC_BC_EXTRAP && a != MFC_BC_PERIODIC) || (b != MFC_BC_EXTRAP && b != MFC_BC_PERIODIC))
+            return fail(MFC_E_ARG, "unknown boundary condition");
+        if ((a == MFC_BC_PERIODIC) != (b == MFC_BC_PERIODIC))
+            return fail(MFC_E_ARG, "periodic must be set on both faces of a dimension");
+    }
+    for (int f = 0; f < 2; f++) {
+        if (!(d->gamma[f] > 1.0) || !std::isfinite(d->gamma[f])) return fail(MFC_E_ARG, "gamma must be > 1");
+        if (!(d->pi_inf[f] >= 0.0) || !std::isfinite(d->pi_inf[f])) return fail(MFC_E_ARG, "pi_inf must be >= 0");
+    }
+    if (!(d->weno_eps > 0.0)) return fail(MFC_E_ARG, "weno_eps must be > 0");
+    if (d->precision != MFC_FP64 && d->precision != MFC_FP32_MIXED) return fail(MFC_E_ARG, "unknown precision");
+    if (d->recon != MFC_RECON_WENO5 && d->recon != MFC_RECON_LEARNED) return fail(MFC_E_ARG, "unknown recon");
+    if (d->kernel != MFC_KERNEL_FUSED && d->kernel != MFC_KERNEL_STAGED) return fail(MFC_E_ARG, "unknown kernel");
+    if (d->precision != MFC_FP64) return fail(MFC_E_UNSUPPORTED, "only MFC_FP64 is built in this version");
+    if (d->recon != MFC_RECON_WENO5) return fail(MFC_E_UNSUPPORTED, "only MFC_RECON_WENO5 is built in this version");
+    return MFC_OK;
+}
+
+bool bad_handle(const mfc_grid *h) { return h == nullptr; }
+
+int set_device(mfc_grid *h)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(MFC_E_HIP, "hipGetDevice failed");
+    if (cur != h->device) return fail(MFC_E_ARG, "handle belongs to another device than the current one");
+    return MFC_OK;
+}
+
+template <class F>
+int by_ndim(int ndim, F f)
+{
+    switch (ndim) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    default: return f(std::integral_constant<int, 3>{});
+    }
+}
+
+int rhs_dispatch(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+                 const double *dt_dev, hipStream_t s)
+{
+    if (h->desc.kernel == MFC_KERNEL_STAGED) return launch_rhs_staged(h, q, q0, out, mode, dt, dt_dev, s);
+    return launch_rhs_fused(h, q, q0, out, mode, dt, dt_dev, s);
+}
+
+int fill_ghosts(mfc_grid *h, double *q, hipStream_t s)
+{
+    const Grid &g = h->g;
+    for (int d = 0; d < g.ndim; d++) {
+        int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+        int64_t count = (int64_t)2 * NG * g.n[o1] * g.n[o2] * h->nvar;
+        hipLaunchKernelGGL(k_ghosts, dim3(blocks_for(count)), dim3(kThreads), 0, s, g, q, h->nvar, d,
+                           h->desc.bc[2 * d], h->desc.bc[2 * d + 1]);
+    }
+    return hip_status(hipGetLastError(), "ghost fill launch");
+}
+
+int wavespeed(mfc_grid *h, const double *q, hipStream_t s)
+{
+    by_ndim(h->g.ndim, [&](auto nd) {
+        hipLaunchKernelGGL((k_wavespeed<decltype(nd)::value>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, h->g, q,
+                           h->partial, h->flag);
+        return 0;
+    });
+    return hip_status(hipGetLastError(), "wave-speed launch");
+}
+
+int64_t state_bytes(const mfc_grid *h) { return (int64_t)h->nvar * h->cells_padded * 8; }
+
+}  // namespace
+}  // namespace mfc
+
+using namespace mfc;
+
+extern "C" {
+
+const char *mfc_strerror(int status)
+{
+    switch (status) {
+    case MFC_OK: return "ok";
+    case MFC_E_ARG: return "invalid argument";
+    case MFC_E_NOMEM: return "out of device memory";
+    case MFC_E_HIP: return "HIP runtime error";
+    case MFC_E_NONPHYSICAL: return "non-physical state (rho <= 0, c^2 <= 0 or non-finite)";
+    case MFC_E_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+    }
+}
+
+const char *mfc_last_error_detail(void) { return g_detail; }
+
+int mfc_free_grid(mfc_grid *h)
+{
+    if (!h) return MFC_OK;
+    (void)hipDeviceSynchronize();
+    for (void *p : {(void *)h->stage_a, (void *)h->stage_b, (void *)h->prim, (void *)h->recp, (void *)h->recm,
+                    (void *)h->faces, (void *)h->partial, (void *)h->scalars, (void *)h->flag})
+        if (p) (void)hipFree(p);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return MFC_OK;
+}
+
+int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
+{
+    if (!out) return fail(MFC_E_ARG, "out is NULL");
+    *out = nullptr;
+    int st = validate(desc);
+    if (st != MFC_OK) return st;
+    mfc_grid *h = new (std::nothrow) mfc_grid();
+    if (!h) return fail(MFC_E_NOMEM, "host allocation failed");
+    h->desc = *desc;
+    Grid &g = h->g;
+    g.ndim = desc->ndim;
+    h->nvar = 4 + desc->ndim;
+    for (int d = 0; d < 3; d++) {
+        bool act = d < desc->ndim;
+        g.n[d] = act ? desc->n[d] : 1;
+        g.off[d] = act ? NG : 0;
+        g.p[d] = act ? desc->n[d] + 2 * NG : 1;
+        g.inv_dx[d] = act ? desc->n[d] / (desc->hi[d] - desc->lo[d]) : 0.0;
+        if (!act) {
+            h->desc.n[d] = 1;
+            h->desc.bc[2 * d] = h->desc.bc[2 * d + 1] = MFC_BC_EXTRAP;
+        }
+    }
+    g.dxmin = 1e300;
+    for (int d = 0; d < desc->ndim; d++) g.dxmin = std::fmin(g.dxmin, (desc->hi[d] - desc->lo[d]) / desc->n[d]);
+    g.stride[0] = 1;
+    g.stride[1] = g.p[0];
+    g.stride[2] = (int64_t)g.p[0] * g.p[1];
+    g.vstride = (int64_t)g.p[0] * g.p[1] * g.p[2];
+    g.g1 = 1.0 / (desc->gamma[0] - 1.0);
+    g.g2 = 1.0 / (desc->gamma[1] - 1.0);
+    g.h1 = desc->gamma[0] * desc->pi_inf[0] / (desc->gamma[0] - 1.0);
+    g.h2 = desc->gamma[1] * desc->pi_inf[1] / (desc->gamma[1] - 1.0);
+    g.eps = desc->weno_eps;
+    h->cells_padded = g.vstride;
+    h->cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(MFC_E_HIP, "hipGetDevice failed");
+    }
+
+    int64_t sb = state_bytes(h);
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void **p, int64_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, (size_t)bytes);
+    };
+    alloc(&h->stage_a, sb);
+    alloc(&h->stage_b, sb);
+    if (desc->kernel == MFC_KERNEL_STAGED) {
+        alloc((void **)&h->prim, sb);
+        alloc((void **)&h->recp, sb);
+        alloc((void **)&h->recm, sb);
+        alloc((void **)&h->faces, (int64_t)3 * (h->nvar + 1) * h->cells_padded * 8);
+    }
+    alloc((void **)&h->partial, kReduceBlocks * 8);
+    alloc((void **)&h->scalars, 4 * 8);
+    alloc((void **)&h->flag, 8);
+    if (e != hipSuccess) {
+        mfc_free_grid(h);
+        return hip_status(e, "scratch allocation");
+    }
+    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, 0, h->scalars, h->flag, 3);
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        mfc_free_grid(h);
+        return hip_status(e, "initialisation");
+    }
+    *out = h;
+    return MFC_OK;
+}
+
+int mfc_state_layout(const mfc_grid *h, int64_t *nvar, int64_t padded[3], int64_t *elem_bytes)
+{
+    if (bad_handle(h)) return fail(MFC_E_ARG, "handle is NULL");
+    if (nvar) *nvar = h->nvar;
+    if (padded)
+        for (int d = 0; d < 3; d++) padded[d] = h->g.p[d];
+    if (elem_bytes) *elem_bytes = h->desc.precision == MFC_FP64 ? 8 : 4;
+    return MFC_OK;
+}
+
+int mfc_prim_to_cons(mfc_grid *h, const void *w, void *q, void *stream)
+{
+    if (bad_handle(h) || !w || !q) return fail(MFC_E_ARG, "null argument");
+    if (w == q) return fail(MFC_E_ARG, "w and q must be distinct");
+    int st = set_device(h);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    by_ndim(h->g.ndim, [&](auto nd) {
+        hipLaunchKernelGGL((k_p2c<decltype(nd)::value>), dim3(blocks_for(h->cells_padded)), dim3(kThreads), 0, s,
+                           h->g, (const double *)w, (double *)q);
+        return 0;
+    });
+    return hip_status(hipGetLastError(), "prim_to_cons launch");
+}
+
+int mfc_cons_to_prim(mfc_grid *h, const void *q, void *w, void *stream)
+{
+    if (bad_handle(h) || !w || !q) return fail(MFC_E_ARG, "null argument");
+    if (w == q) return fail(MFC_E_ARG, "w and q must be distinct");
+    int st = set_device(h);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    by_ndim(h->g.ndim, [&](auto nd) {
+        hipLaunchKernelGGL((k_c2p<decltype(nd)::value>), dim3(blocks_for(h->cells_padded)), dim3(kThreads), 0, s,
+                           h->g, (const double *)q, (double *)w, h->flag);
+        return 0;
+    });
+    return hip_status(hipGetLastError(), "cons_to_prim launch");
+}
+
+int mfc_fill_ghosts(mfc_grid *h, void *q, void *stream)
+{
+    if (bad_handle(h) || !q) return fail(MFC_E_ARG, "null argument");
+    int st = set_device(h);
+    if (st) return st;
+    return fill_ghosts(h, (double *)q, (hipStream_t)stream);
+}
+
+int mfc_rhs(mfc_grid *h, const void *q, void *rhs, void *stream)
+{
+    if (bad_handle(h) || !q || !rhs) return fail(MFC_E_ARG, "null argument");
+    if (q == rhs) return fail(MFC_E_ARG, "q and rhs must be distinct");
+    int st = set_device(h);
+    if (st) return st;
+    return rhs_dispatch(h, (const double *)q, nullptr, (double *)rhs, 0, 0.0, nullptr, (hipStream_t)stream);
+}
+
+int mfc_max_wavespeed(mfc_grid *h, const void *q, double *smax_host, void *stream)
+{
+    if (bad_handle(h) || !q || !smax_host) return fail(MFC_E_ARG, "null argument");
+    int st = set_device(h);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = wavespeed(h, (const double *)q, s);
+    if (st) return st;
+    double *partial = (double *)std::malloc(kReduceBlocks * sizeof(double));
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(partial, h->partial, kReduceBlocks * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        std::free(partial);
+        return hip_status(e, "wave-speed readback");
+    }
+    double m = 0.0;
+    for (int b = 0; b < kReduceBlocks; b++) m = std::fmax(m, partial[b]);
+    std::free(partial);
+    *smax_host = m;
+    if (flag & 2) {
+        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, h->scalars, h->flag, 2);
+        return fail(MFC_E_NONPHYSICAL, "non-physical interior cell in the wave-speed reduction");
+    }
+    return MFC_OK;
+}
+
+int mfc_rk3_step(mfc_grid *h, void *qv, double cfl, double dt, void *stream)
+{
+    if (bad_handle(h) || !qv) return fail(MFC_E_ARG, "null argument");
+    if (!(cfl > 0.0) && !(dt > 0.0)) return fail(MFC_E_ARG, "need cfl > 0 or dt > 0");
+    if (!std::isfinite(cfl) || !std::isfinite(dt)) return fail(MFC_E_ARG, "cfl and dt must be finite");
+    int st = set_device(h);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double *q = (double *)qv, *A = (double *)h->stage_a, *B = (double *)h->stage_b;
+    const double *dt_dev = h->scalars + 1;
+    if ((st = fill_ghosts(h, q, s))) return st;
+    if (cfl > 0.0) {
+        if ((st = wavespeed(h, q, s))) return st;
+        hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(kReduceThreads), 0, s, h->partial, kReduceBlocks, cfl, 0.0,
+                           h->g.dxmin, h->scalars);
+    } else {
+        hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(kReduceThreads), 0, s, nullptr, 0, 0.0, dt, h->g.dxmin,
+                           h->scalars);
+    }
+    if ((st = rhs_dispatch(h, q, q, A, 1, 0.0, dt_dev, s))) return st;
+    if ((st = fill_ghosts(h, A, s))) return st;
+    if ((st = rhs_dispatch(h, A, q, B, 2, 0.0, dt_dev, s))) return st;
+    if ((st = fill_ghosts(h, B, s))) return st;
+    if ((st = rhs_dispatch(h, B, q, q, 3, 0.0, dt_dev, s))) return st;
+    return hip_status(hipGetLastError(), "rk3 step launch");
+}
+
+int mfc_run(mfc_grid *h, void *q, int nsteps, double cfl, double dt, void *stream)
+{
+    if (nsteps < 0) return fail(MFC_E_ARG, "nsteps must be >= 0");
+    for (int n = 0; n < nsteps; n++) {
+        int st = mfc_rk3_step(h, q, cfl, dt, stream);
+        if (st) return st;
+    }
+    return MFC_OK;
+}
+
+int mfc_time(mfc_grid *h, double *t_host, double *last_dt_host, void *stream)
+{
+    if (bad_handle(h)) return fail(MFC_E_ARG, "handle is NULL");
+    int st = set_device(h);
+    if (st) return st;
+    double sc[4];
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(sc, h->scalars, sizeof sc, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, "time readback");
+    if (t_host) *t_host = sc[2];
+    if (last_dt_host) *last_dt_host = sc[1];
+    return MFC_OK;
+}
+
+int mfc_reset_time(mfc_grid *h, void *stream)
+{
+    if (bad_handle(h)) return fail(MFC_E_ARG, "handle is NULL");
+    int st = set_device(h);
+    if (st) return st;
+    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, (hipStream_t)stream, h->scalars, h->flag, 1);
+    return hip_status(hipGetLastError(), "reset time");
+}
+
+int mfc_check(mfc_grid *h, void *stream)
+{
+    if (bad_handle(h)) return fail(MFC_E_ARG, "handle is NULL");
+    int st = set_device(h);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, "flag readback");
+    if (flag) {
+        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, h->scalars, h->flag, 2);
+        return fail(MFC_E_NONPHYSICAL, "a kernel met a non-physical cell");
+    }
+    return MFC_OK;
+}
+
+int mfc_set_kernel_timing(mfc_grid *h, int enable)
+{
+    if (bad_handle(h)) return fail(MFC_E_ARG, "handle is NULL");
+    h->timing = enable != 0;
+    h->ev_used = 0;
+    return MFC_OK;
+}
+
+int mfc_kernel_time(mfc_grid *h, double *ms_total, int64_t *launches)
+{
+    if (bad_handle(h) || !ms_total || !launches) return fail(MFC_E_ARG, "null argument");
+    double total = 0.0;
+    for (size_t p = 0; p + 1 < h->ev_used; p += 2) {
+        hipError_t e = hipEventSynchronize(h->ev[p + 1]);
+        if (e != hipSuccess) return hip_status(e, "event sync");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, h->ev[p], h->ev[p + 1]);
+        if (e != hipSuccess) return hip_status(e, "event elapsed time");
+        total += ms;
+    }
+    *ms_total = total;
+    *launches = (int64_t)(h->ev_used / 2);
+    h->ev_used = 0;
+    return MFC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+"""Python binding of the C ABI in include/mfc.h (ctypes; argument marshalling only).
+
+Every step of the right-hand side runs in the HIP kernels of ``libmfc.so``;
+PyTorch supplies device memory (tensors of the state layout) and the stream.
+The binding refuses to run if the library has not been built: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mfc.h")
+
+MFC_OK = 0
+MFC_E_ARG = -1
+MFC_E_NOMEM = -2
+MFC_E_HIP = -3
+MFC_E_NONPHYSICAL = -4
+MFC_E_UNSUPPORTED = -5
+MFC_BC_EXTRAP, MFC_BC_PERIODIC = 0, 1
+MFC_FP64, MFC_FP32_MIXED = 0, 1
+MFC_RECON_WENO5, MFC_RECON_LEARNED = 0, 1
+MFC_KERNEL_FUSED, MFC_KERNEL_STAGED = 0, 1
+
+
+class MfcError(RuntimeError):
+    def __init__(self, status: int, call: str, detail: str):
+        super().__init__(f"{call} failed: {status} ({detail})")
+        self.status = status
+
+
+class mfc_grid_desc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("num_fluids", ctypes.c_int), ("gamma", ctypes.c_double * 2),
+                ("pi_inf", ctypes.c_double * 2), ("bc", ctypes.c_int * 6), ("precision", ctypes.c_int),
+                ("recon", ctypes.c_int), ("weno_eps", ctypes.c_double), ("kernel", ctypes.c_int)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_SIGNATURES = {
+    "mfc_init_grid": [ctypes.POINTER(mfc_grid_desc), ctypes.POINTER(_VP)],
+    "mfc_free_grid": [_VP],
+    "mfc_state_layout": [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                         ctypes.POINTER(ctypes.c_int64)],
+    "mfc_prim_to_cons": [_VP, _VP, _VP, _VP],
+    "mfc_cons_to_prim": [_VP, _VP, _VP, _VP],
+    "mfc_fill_ghosts": [_VP, _VP, _VP],
+    "mfc_rhs": [_VP, _VP, _VP, _VP],
+    "mfc_max_wavespeed": [_VP, _VP, ctypes.POINTER(ctypes.c_double), _VP],
+    "mfc_rk3_step": [_VP, _VP, ctypes.c_double, ctypes.c_double, _VP],
+    "mfc_run": [_VP, _VP, ctypes.c_int, ctypes.c_double, ctypes.c_double, _VP],
+    "mfc_time": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _VP],
+    "mfc_reset_time": [_VP, _VP],
+    "mfc_check": [_VP, _VP],
+    "mfc_set_kernel_timing": [_VP, ctypes.c_int],
+    "mfc_kernel_time": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+}
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions include/mfc.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(mfc_\w+)\s*\(", text, re.M)))
+
+
+def lib():
+    """Load libmfc.so (after torch, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python __graft_entry__.py build` "
+                               "(or paper_2305_09163_amd/build.py) first; there is no CPU fallback")
+        import torch  # noqa: F401  (loads the HIP runtime the library then shares)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.mfc_strerror.argtypes = [ctypes.c_int]
+        L.mfc_strerror.restype = ctypes.c_char_p
+        L.mfc_last_error_detail.argtypes = []
+        L.mfc_last_error_detail.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int, call: str):
+    if status != MFC_OK:
+        L = lib()
+        raise MfcError(status, call, f"{L.mfc_strerror(status).decode()}: {L.mfc_last_error_detail().decode()}")
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _VP(stream.cuda_stream)
+
+
+def _ptr(t):
+    return _VP(t.data_ptr())
+
+
+def make_desc(spec, precision: int = MFC_FP64, recon: int = MFC_RECON_WENO5,
+              kernel: int = MFC_KERNEL_FUSED) -> mfc_grid_desc:
+    """C descriptor from a GridSpec-like object (ndim, n, lo, hi, gamma, pi_inf, bc, weno_eps)."""
+    d = mfc_grid_desc()
+    d.ndim = spec.ndim
+    for k in range(3):
+        d.n[k] = spec.n[k]
+        d.lo[k] = spec.lo[k]
+        d.hi[k] = spec.hi[k]
+    d.num_fluids = 2
+    d.gamma[0], d.gamma[1] = spec.gamma
+    d.pi_inf[0], d.pi_inf[1] = spec.pi_inf
+    for f in range(6):
+        d.bc[f] = spec.bc[f]
+    d.precision = precision
+    d.recon = recon
+    d.weno_eps = spec.weno_eps
+    d.kernel = kernel
+    return d
+
+
+# ---------------------------------------------------------------------------
+# Thin wrappers with the C names (status codes raised as MfcError)
+# ---------------------------------------------------------------------------
+
+def mfc_init_grid(desc: mfc_grid_desc) -> ctypes.c_void_p:
+    h = _VP()
+    _check(lib().mfc_init_grid(ctypes.byref(desc), ctypes.byref(h)), "mfc_init_grid")
+    return h
+
+
+def mfc_free_grid(h):
+    _check(lib().mfc_free_grid(h), "mfc_free_grid")
+
+
+def mfc_state_layout(h):
+    nv, eb = ctypes.c_int64(), ctypes.c_int64()
+    pad = (ctypes.c_int64 * 3)()
+    _check(lib().mfc_state_layout(h, ctypes.byref(nv), pad, ctypes.byref(eb)), "mfc_state_layout")
+    return nv.value, tuple(pad), eb.value
+
+
+def mfc_prim_to_cons(h, w, q, stream=None):
+    _check(lib().mfc_prim_to_cons(h, _ptr(w), _ptr(q), _stream(stream)), "mfc_prim_to_cons")
+
+
+def mfc_cons_to_prim(h, q, w, stream=None):
+    _check(lib().mfc_cons_to_prim(h, _ptr(q), _ptr(w), _stream(stream)), "mfc_cons_to_prim")
+
+
+def mfc_fill_ghosts(h, q, stream=None):
+    _check(lib().mfc_fill_ghosts(h, _ptr(q), _stream(stream)), "mfc_fill_ghosts")
+
+
+def mfc_rhs(h, q, rhs, stream=None):
+    _check(lib().mfc_rhs(h, _ptr(q), _ptr(rhs), _stream(stream)), "mfc_rhs")
+
+
+def mfc_max_wavespeed(h, q, stream=None) -> float:
+    s = ctypes.c_double()
+    _check(lib().mfc_max_wavespeed(h, _ptr(q), ctypes.byref(s), _stream(stream)), "mfc_max_wavespeed")
+    return s.value
+
+
+def mfc_rk3_step(h, q, cfl: float = 0.0, dt: float = 0.0, stream=None):
+    _check(lib().mfc_rk3_step(h, _ptr(q), cfl, dt, _stream(stream)), "mfc_rk3_step")
+
+
+def mfc_run(h, q, nsteps: int, cfl: float = 0.0, dt: float = 0.0, stream=None):
+    _check(lib().mfc_run(h, _ptr(q), nsteps, cfl, dt, _stream(stream)), "mfc_run")
+
+
+def mfc_time(h, stream=None):
+    t, dt = ctypes.c_double(), ctypes.c_double()
+    _check(lib().mfc_time(h, ctypes.byref(t), ctypes.byref(dt), _stream(stream)), "mfc_time")
+    return t.value, dt.value
+
+
+def mfc_reset_time(h, stream=None):
+    _check(lib().mfc_reset_time(h, _stream(stream)), "mfc_reset_time")
+
+
+def mfc_check(h, stream=None):
+    _check(lib().mfc_check(h, _stream(stream)), "mfc_check")
+
+
+def mfc_set_kernel_timing(h, enable: bool):
+    _check(lib().mfc_set_kernel_timing(h, int(enable)), "mfc_set_kernel_timing")
+
+
+def mfc_kernel_time(h):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().mfc_kernel_time(h, ctypes.byref(ms), ctypes.byref(n)), "mfc_kernel_time")
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------------------
+# Convenience object
+# ---------------------------------------------------------------------------
+
+class Solver:
+    """A grid handle plus torch-allocated state helpers."""
+
+    def __init__(self, spec, precision: int = MFC_FP64, recon: int = MFC_RECON_WENO5,
+                 kernel: int = MFC_KERNEL_FUSED):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible; the library runs on the GPU only")
+        self.spec = spec
+        self.desc = make_desc(spec, precision, recon, kernel)
+        self.h = mfc_init_grid(self.desc)
+        nv, pad, eb = mfc_state_layout(self.h)
+        self.shape = (nv, pad[2], pad[1], pad[0])
+        self.dtype = torch.float64 if eb == 8 else torch.float32
+
+    def close(self):
+        if self.h:
+            mfc_free_grid(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self):
+        import torch
+        return torch.empty(self.shape, dtype=self.dtype, device="cuda")
+
+    def state_from_prim(self, w_host):
+        """Conservative device state from a host primitive array (converted on the GPU)."""
+        import torch
+        w = torch.as_tensor(w_host, dtype=self.dtype).to("cuda")
+        q = self.empty()
+        mfc_prim_to_cons(self.h, w, q)
+        return q
+
+    def fill_ghosts(self, q):
+        mfc_fill_ghosts(self.h, q)
+
+    def rhs(self, q, out=None):
+        import torch
+        if out is None:
+            out = torch.zeros_like(q)
+        mfc_rhs(self.h, q, out)
+        return out
+
+    def max_wavespeed(self, q):
+        return mfc_max_wavespeed(self.h, q)
+
+    def step(self, q, cfl=0.0, dt=0.0):
+        mfc_rk3_step(self.h, q, cfl, dt)
+
+    def run(self, q, nsteps, cfl=0.0, dt=0.0):
+        mfc_run(self.h, q, nsteps, cfl, dt)
+
+    def time(self):
+        return mfc_time(self.h)
+
+    def check(self):
+        mfc_check(self.h)

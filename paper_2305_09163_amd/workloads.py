@@ -160,8 +160,10 @@ def bubble_collapse_3d(n: int = 128, seed_offset: int = 2, noise: float = 0.01, 
     R0 (1 + noise * S / max|S|) carries seeded real spherical-harmonic noise
     (l = 2..8, a_lm ~ N(0, 1)), and the interface is smeared by
     H = (1 + tanh((r - R)/dx))/2; alpha1 = a_min + (1 - 2 a_min) H, and the
-    same H blends the pressure.  noise = 0 gives an exactly centred sphere."""
-    spec = GridSpec(ndim=3, n=(n, n, n))
+    same H blends the pressure.  noise = 0 gives an exactly centred sphere.
+    n may be an int (cube) or an (nx, ny, nz) tuple on the same unit cube."""
+    ns = (n, n, n) if isinstance(n, int) else tuple(n)
+    spec = GridSpec(ndim=3, n=ns)
     x, y, z = spec.mesh()
     rx, ry, rz = x - centre[0], y - centre[1], z - centre[2]
     r = np.sqrt(rx * rx + ry * ry + rz * rz)

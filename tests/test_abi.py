@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/mfc.h declares, and rejects invalid arguments with
+the documented status codes before touching the device."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2305_09163_amd import mfc
+from paper_2305_09163_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(mfc.LIB_PATH):
+        pytest.fail("libmfc.so is not built (run __graft_entry__.build())")
+    return mfc.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = mfc.header_symbols()
+    assert "mfc_rhs" in names and "mfc_rk3_step" in names and len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_strerror(L):
+    for code in (mfc.MFC_OK, mfc.MFC_E_ARG, mfc.MFC_E_NOMEM, mfc.MFC_E_HIP, mfc.MFC_E_NONPHYSICAL,
+                 mfc.MFC_E_UNSUPPORTED):
+        assert len(L.mfc_strerror(code)) > 0
+    assert L.mfc_strerror(12345) == b"unknown status"
+
+
+def desc(**kw):
+    spec = W.GridSpec(ndim=3, n=(8, 8, 8))
+    d = mfc.make_desc(spec, kernel=mfc.MFC_KERNEL_STAGED)
+    for k, v in kw.items():
+        if isinstance(v, (list, tuple)):
+            arr = getattr(d, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ndim=0), mfc.MFC_E_ARG),
+    (dict(ndim=4), mfc.MFC_E_ARG),
+    (dict(n=(2, 8, 8)), mfc.MFC_E_ARG),
+    (dict(num_fluids=3), mfc.MFC_E_UNSUPPORTED),
+    (dict(gamma=(1.0, 1.4)), mfc.MFC_E_ARG),
+    (dict(pi_inf=(-1.0, 0.0)), mfc.MFC_E_ARG),
+    (dict(hi=(0.0, 1.0, 1.0)), mfc.MFC_E_ARG),
+    (dict(bc=(1, 0, 0, 0, 0, 0)), mfc.MFC_E_ARG),
+    (dict(bc=(7, 7, 0, 0, 0, 0)), mfc.MFC_E_ARG),
+    (dict(weno_eps=0.0), mfc.MFC_E_ARG),
+    (dict(precision=9), mfc.MFC_E_ARG),
+    (dict(kernel=9), mfc.MFC_E_ARG),
+])
+def test_init_rejects_invalid_descriptors(L, kw, code):
+    h = ctypes.c_void_p(123)
+    st = L.mfc_init_grid(ctypes.byref(desc(**kw)), ctypes.byref(h))
+    assert st == code
+    assert h.value is None
+    assert len(L.mfc_last_error_detail()) > 0
+
+
+def test_null_arguments(L):
+    assert L.mfc_init_grid(None, None) == mfc.MFC_E_ARG
+    h = ctypes.c_void_p()
+    assert L.mfc_init_grid(None, ctypes.byref(h)) == mfc.MFC_E_ARG
+    for name in ("mfc_fill_ghosts", "mfc_check", "mfc_reset_time"):
+        f = getattr(L, name)
+        args = [None] * (len(f.argtypes))
+        assert f(*args) == mfc.MFC_E_ARG, name
+    assert L.mfc_rhs(None, None, None, None) == mfc.MFC_E_ARG
+    assert L.mfc_rk3_step(None, None, 0.3, 0.0, None) == mfc.MFC_E_ARG
+    assert L.mfc_free_grid(None) == mfc.MFC_OK
