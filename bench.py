@@ -1,0 +1,133 @@
+#!/usr/bin/env python3
+"""Throughput of the right-hand side of the two-fluid five-equation model
+(WENO5-JS + HLLC + SSP-RK3) on one MI355X.
+
+Workload: the 3D air-bubble collapse in water on 128^3 cells (7 state
+variables, FP64, CFL 0.3, seeded spherical-harmonic surface noise), state
+resident in HBM.  A step is one full SSP-RK3 step: ghost fill, the CFL
+wave-speed reduction and three fused right-hand-side launches.  The metric
+is RHS cell-updates/s = interior cells x 3 stages x steps / wall time.
+
+One JSON line is printed.  `roofline` is measured on the dominant kernel (the
+fused right-hand side) with HIP events recorded by the library around every
+launch of it on the launch stream during the timed region.  `cpu_baseline`
+times the FP64 CPU oracle on the host for one SSP-RK3 step of the same
+workload.
+
+    python bench.py [--steps K] [--warmup W] [--n 128] [--kernel fused|staged]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RHS cell-updates/s (WENO5+HLLC), FP64 vs FP32/learned at fixed L1 error"
+
+# Algorithmic work per RHS cell-update, counted from the FP64 oracle's
+# formulation (every +, -, *, / and sqrt is one flop; material constants
+# precomputed; one reconstruction and one face per cell and direction):
+# conservative->primitive 28, WENO5 88 x 7 variables x 3 directions = 1848,
+# HLLC 146 x 3 = 438, flux differences + div(u) source 74, stage update 28.
+FLOPS_PER_CELL_UPDATE = 2416
+# Bytes per cell-update of one fused pass, averaged over the three stages:
+# read the stage input (56 B), read q^n on stages 2 and 3 (56 B), write the
+# result (56 B): (112 + 168 + 168) / 3.
+BYTES_PER_CELL_UPDATE = (112 + 168 + 168) / 3
+PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
+PEAK_HBM = 8.0e12
+
+
+def cpu_baseline(spec, w):
+    import oracle
+
+    q = oracle.prim_to_cons_field(spec, w)
+    t0 = time.perf_counter()
+    _, _, st = oracle.run(spec, q, 1, cfl=0.3)
+    el = time.perf_counter() - t0
+    assert st == oracle.OK
+    return {"value": spec.cells * 3 / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 SSP-RK3 step (3 RHS evaluations) of the {spec.n[0]}^3 bubble workload, "
+                      f"single-threaded C oracle (gcc -O2), {el:.1f} s",
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--kernel", choices=["fused", "staged"], default="fused")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2305_09163_amd import mfc
+    from paper_2305_09163_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    spec, w = W.bubble_collapse_3d(n=args.n)
+    kernel = mfc.MFC_KERNEL_FUSED if args.kernel == "fused" else mfc.MFC_KERNEL_STAGED
+    solver = mfc.Solver(spec, kernel=kernel)
+    q = solver.state_from_prim(w)
+    cfl = 0.3
+    for _ in range(args.warmup):
+        solver.step(q, cfl=cfl)
+    torch.cuda.synchronize()
+    solver.check()
+
+    mfc.mfc_set_kernel_timing(solver.h, True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        solver.step(q, cfl=cfl)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_kernel, launches = mfc.mfc_kernel_time(solver.h)
+    mfc.mfc_set_kernel_timing(solver.h, False)
+    solver.check()
+    ev_s = e0.elapsed_time(e1) / 1e3
+    elapsed = max(wall, ev_s)
+
+    updates = spec.cells * 3 * args.steps
+    value = updates / elapsed
+    avg_launch = ms_kernel / 1e3 / max(launches, 1)
+    flops_launch = FLOPS_PER_CELL_UPDATE * spec.cells
+    bytes_launch = BYTES_PER_CELL_UPDATE * spec.cells
+    achieved = flops_launch / avg_launch
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+            "kernel": "k_fused<3> (fused RHS + stage update)", "launches": launches,
+            "avg_launch_us": avg_launch * 1e6,
+            "flops_per_cell_update": FLOPS_PER_CELL_UPDATE,
+            "hbm_algorithmic_GBps": bytes_launch / avg_launch / 1e9,
+            "hbm_frac": bytes_launch / avg_launch / PEAK_HBM}
+    t, _ = solver.time()
+    out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"bubble_collapse_3d_{args.n}", "cells": spec.cells, "nvar": spec.nvar,
+                      "cfl": cfl, "precision": "fp64", "kernel": args.kernel, "recon": "weno5",
+                      "parallelism": "single GPU"},
+           "roofline": roof, "simulated_time_s": t}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

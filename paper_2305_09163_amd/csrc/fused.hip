@@ -1,11 +1,279 @@
-// Fused right-hand side (placeholder until the LDS-tiled kernel lands).
+// Fused right-hand side: one launch per Runge-Kutta stage evaluates the whole
+// semi-discrete operator of eq. (fvmdis) (Sec. 3.1) for a block of cells and
+// writes the stage result, so the state is read once and written once.
+//
+// Work decomposition (3D).  A workgroup of 16 x 16 threads owns a 16 x 16
+// column of cells in (x, y) and marches through a chunk of z planes:
+//   - z: each thread keeps the primitives of planes k-1 .. k+3 of its own
+//     column in registers, reconstructs cell k+1 (WENO5, both faces) and
+//     solves the Riemann problem at face k+1/2 (Sec. 3.2, 3.2.1); the flux of
+//     face k-1/2 is carried over from the previous plane;
+//   - x and y: plane k (with 3-cell halos) is converted to primitives into
+//     LDS once; every cell of the tile plus one halo cell per side is
+//     reconstructed once per direction (both face values from one stencil),
+//     the pair values go to LDS, and the HLLC flux of every face of the tile
+//     is computed once and shared by the two cells that own the face;
+//   - each thread then forms its cell's flux differences plus the
+//     alpha1 div(u) source and the SSP-RK3 stage combination.
+// 2D uses the same tile without the z march; 1D uses a 256-cell row.
 #include "internal.h"
 
 namespace mfc {
+namespace {
 
-int launch_rhs_fused(mfc_grid *, const double *, const double *, double *, int, double, const double *, hipStream_t)
+template <int NDIM>
+struct Shape {
+    static constexpr int TX = NDIM == 1 ? 256 : 16;
+    static constexpr int TY = NDIM == 1 ? 1 : 16;
+    static constexpr int NT = TX * TY;
+    static constexpr int NV = 4 + NDIM;
+    static constexpr int PX = TX + 2 * NG;
+    static constexpr int PY = NDIM >= 2 ? TY + 2 * NG : 1;
+    static constexpr int OY = NDIM >= 2 ? NG : 0;   // LDS row of the tile's first row
+    static constexpr int NPX = (TX + 2) * TY;       // x reconstructions (cells -1 .. TX)
+    static constexpr int NFX = (TX + 1) * TY;       // x faces
+    static constexpr int NPY = NDIM >= 2 ? TX * (TY + 2) : 0;
+    static constexpr int NFY = NDIM >= 2 ? TX * (TY + 1) : 0;
+    static constexpr int NP = NPX > NPY ? NPX : NPY;
+    static constexpr int NF = NFX > NFY ? NFX : NFY;
+    static constexpr int NHALO = 2 * NG * TY + (NDIM >= 2 ? 2 * NG * TX : 0);
+};
+
+constexpr int kLZ = 16;  // z planes per workgroup
+
+// Load one cell and convert it to primitives.  Returns true if the cell is
+// non-physical AND is one the method reads (interior or ghost face slab: at
+// most one coordinate outside the interior).  Lanes past a ragged grid edge
+// may load edge/corner ghost cells, which are never written; their values
+// only feed lanes whose results are discarded, so they must not raise the
+// flag either.
+template <int NDIM>
+__device__ __forceinline__ bool load_prim(const Grid &g, const double *__restrict__ q, int i, int j, int k,
+                                          double *w)
 {
-    return fail(MFC_E_UNSUPPORTED, "fused kernel not built yet; use MFC_KERNEL_STAGED");
+    constexpr int NV = 4 + NDIM;
+    const int64_t c = (int64_t)(k + g.off[2]) * g.stride[2] + (int64_t)(j + g.off[1]) * g.stride[1] + (i + g.off[0]);
+    double qc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
+    const bool bad = cons_to_prim<NDIM>(g, qc, w);
+    const int outside = (i < 0 || i >= g.n[0]) + (j < 0 || j >= g.n[1]) + (k < 0 || k >= g.n[2]);
+    return bad && outside <= 1;
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
+    k_fused(Grid g, const double *__restrict__ q, const double *q0, double *out, int mode, double dt,
+            const double *__restrict__ dt_dev, int *__restrict__ flag, int lz)
+{
+    using S = Shape<NDIM>;
+    constexpr int NV = S::NV, A = 3 + NDIM, TX = S::TX, TY = S::TY, NT = S::NT, OY = S::OY;
+    __shared__ double s_plane[NV][S::PY][S::PX];
+    __shared__ double s_pair[2 * NV][S::NP];
+    __shared__ double s_flux[NV + 1][S::NF];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int z0 = NDIM == 3 ? (int)blockIdx.z * lz : 0;
+    const int z1 = NDIM == 3 ? min(z0 + lz, g.n[2]) : 1;
+    const int xmax = g.n[0] + NG - 1;                  // last readable cell (ghost)
+    const int ymax = NDIM >= 2 ? g.n[1] + NG - 1 : 0;
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool own = gx < g.n[0] && gy < g.n[1];
+    const int cx = min(gx, xmax), cy = min(gy, ymax);  // clamped: out-of-grid lanes read real cells
+    bool bad = false;
+
+    // ---- z march state (3D): primitives of planes k-1 .. k+3 of this column,
+    // the reconstruction of cell k at its + face, the flux at face k-1/2.
+    double zw[5][NV];
+    double pk[NV];
+    double Fz[NV + 1];
+    if constexpr (NDIM == 3) {
+#pragma unroll
+        for (int p = 0; p < 5; p++) bad |= load_prim<NDIM>(g, q, cx, cy, z0 - 3 + p, zw[p]);
+        double plus_prev[NV], mk[NV], dummy;
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], g.eps, plus_prev[v], dummy);
+#pragma unroll
+        for (int p = 0; p < 4; p++)
+#pragma unroll
+            for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
+        bad |= load_prim<NDIM>(g, q, cx, cy, z0 + 2, zw[4]);
+#pragma unroll
+        for (int v = 0; v < NV; v++) weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], g.eps, pk[v], mk[v]);
+        bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0)>(g, plus_prev, mk, Fz, Fz[NV]) && own;
+    }
+
+    const double hdt = mode ? (dt_dev ? *dt_dev : dt) : 0.0;
+    const double ca = mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0);
+    const double cb = mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0);
+
+    for (int k = z0; k < z1; k++) {
+        double wk[NV];
+        double Fzn[NV + 1];
+        if constexpr (NDIM == 3) {
+#pragma unroll
+            for (int p = 0; p < 4; p++)
+#pragma unroll
+                for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
+            bad |= load_prim<NDIM>(g, q, cx, cy, k + 3, zw[4]);
+            double pn[NV], mn[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                wk[v] = zw[1][v];
+                weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], g.eps, pn[v], mn[v]);
+            }
+            bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0)>(g, pk, mn, Fzn, Fzn[NV]) && own;
+#pragma unroll
+            for (int v = 0; v < NV; v++) pk[v] = pn[v];
+        } else {
+            bad |= load_prim<NDIM>(g, q, cx, cy, 0, wk);
+        }
+
+        // ---- plane k into LDS: own cell, then the x and y halos
+#pragma unroll
+        for (int v = 0; v < NV; v++) s_plane[v][ty + OY][tx + NG] = wk[v];
+        for (int h = tid; h < S::NHALO; h += NT) {
+            int li, lj;
+            if (h < 2 * NG * TY) {
+                const int col = h % (2 * NG), row = h / (2 * NG);
+                li = col < NG ? col : TX + col;
+                lj = row + OY;
+            } else {
+                const int h2 = h - 2 * NG * TY;
+                const int col = h2 % TX, r = h2 / TX;
+                li = col + NG;
+                lj = r < NG ? r : TY + r;
+            }
+            const int gi = min(x0 + li - NG, xmax), gj = min(y0 + lj - OY, ymax);
+            double w[NV];
+            bad |= load_prim<NDIM>(g, q, gi, gj, k, w);
+#pragma unroll
+            for (int v = 0; v < NV; v++) s_plane[v][lj][li] = w[v];
+        }
+        __syncthreads();
+
+        // ---- x: reconstruct cells -1 .. TX of every row
+        for (int p = tid; p < S::NPX; p += NT) {
+            const int row = p / (TX + 2), c = p % (TX + 2);
+            const int lj = row + OY;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const double *s = &s_plane[v][lj][c];
+                weno5_pair(s[0], s[1], s[2], s[3], s[4], g.eps, s_pair[v][p], s_pair[NV + v][p]);
+            }
+        }
+        __syncthreads();
+        // ---- x faces: face fi sits between tile cells fi-1 and fi
+        for (int f = tid; f < S::NFX; f += NT) {
+            const int row = f / (TX + 1), fi = f % (TX + 1);
+            const int pl = row * (TX + 2) + fi;
+            double wL[NV], wR[NV], F[NV], uf;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                wL[v] = s_pair[v][pl];
+                wR[v] = s_pair[NV + v][pl + 1];
+            }
+            const bool b = hllc<NDIM, 0>(g, wL, wR, F, uf);
+            bad |= b && (y0 + row < g.n[1]) && (x0 + fi <= g.n[0]);
+#pragma unroll
+            for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
+            s_flux[NV][f] = uf;
+        }
+        __syncthreads();
+        double L[NV], divu;
+        {
+            const int f = ty * (TX + 1) + tx;
+#pragma unroll
+            for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * g.inv_dx[0];
+            divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * g.inv_dx[0];
+        }
+
+        if constexpr (NDIM >= 2) {
+            // ---- y: reconstruct rows -1 .. TY of every column
+            for (int p = tid; p < S::NPY; p += NT) {
+                const int c = p % TX, r = p / TX;
+                const int li = c + NG;
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li], s_plane[v][r + 3][li],
+                               s_plane[v][r + 4][li], g.eps, s_pair[v][p], s_pair[NV + v][p]);
+            }
+            __syncthreads();
+            for (int f = tid; f < S::NFY; f += NT) {
+                const int c = f % TX, fr = f / TX;
+                const int pl = fr * TX + c;
+                double wL[NV], wR[NV], F[NV], uf;
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    wL[v] = s_pair[v][pl];
+                    wR[v] = s_pair[NV + v][pl + TX];
+                }
+                const bool b = hllc<NDIM, (NDIM >= 2 ? 1 : 0)>(g, wL, wR, F, uf);
+                bad |= b && (x0 + c < g.n[0]) && (y0 + fr <= g.n[1]);
+#pragma unroll
+                for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
+                s_flux[NV][f] = uf;
+            }
+            __syncthreads();
+            const int f = ty * TX + tx;
+#pragma unroll
+            for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * g.inv_dx[1];
+            divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * g.inv_dx[1];
+        }
+        if constexpr (NDIM == 3) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) L[v] += (Fz[v] - Fzn[v]) * g.inv_dx[2];
+            divu += (Fzn[NV] - Fz[NV]) * g.inv_dx[2];
+#pragma unroll
+            for (int v = 0; v <= NV; v++) Fz[v] = Fzn[v];
+        }
+        L[A] += wk[A] * divu;
+
+        if (own) {
+            const int64_t c = (int64_t)(k + g.off[2]) * g.stride[2] + (int64_t)(gy + g.off[1]) * g.stride[1] +
+                              (gx + g.off[0]);
+            if (mode == 0) {
+#pragma unroll
+                for (int v = 0; v < NV; v++) out[v * g.vstride + c] = L[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const int64_t o = v * g.vstride + c;
+                    out[o] = ca * q0[o] + cb * (q[o] + hdt * L[v]);
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+template <int NDIM>
+int rhs_fused(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+              const double *dt_dev, hipStream_t s)
+{
+    using S = Shape<NDIM>;
+    const Grid &g = h->g;
+    dim3 grid((g.n[0] + S::TX - 1) / S::TX, NDIM >= 2 ? (g.n[1] + S::TY - 1) / S::TY : 1,
+              NDIM == 3 ? (g.n[2] + kLZ - 1) / kLZ : 1);
+    timing_begin(h, s);
+    hipLaunchKernelGGL((k_fused<NDIM>), grid, dim3(S::NT), 0, s, g, q, q0, out, mode, dt, dt_dev, h->flag, kLZ);
+    timing_end(h, s);
+    return hip_status(hipGetLastError(), "fused right-hand side launch");
+}
+
+}  // namespace
+
+int launch_rhs_fused(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+                     const double *dt_dev, hipStream_t s)
+{
+    switch (h->g.ndim) {
+    case 1: return rhs_fused<1>(h, q, q0, out, mode, dt, dt_dev, s);
+    case 2: return rhs_fused<2>(h, q, q0, out, mode, dt, dt_dev, s);
+    default: return rhs_fused<3>(h, q, q0, out, mode, dt, dt_dev, s);
+    }
 }
 
 }  // namespace mfc

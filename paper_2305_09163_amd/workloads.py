@@ -174,9 +174,14 @@ def bubble_collapse_3d(n: int = 128, seed_offset: int = 2, noise: float = 0.01, 
         tg = (np.arange(256) + 0.5) * math.pi / 256
         pg = np.arange(512) * 2.0 * math.pi / 512
         smax = np.abs(_real_sph_harm_sum(tg[:, None], pg[None, :], coeffs, lmax)).max()
-        theta = np.arccos(np.clip(rz / np.maximum(r, 1e-300), -1.0, 1.0))
-        phi = np.arctan2(ry, rx)
-        R = radius * (1.0 + noise * _real_sph_harm_sum(theta, phi, coeffs, lmax) / smax)
+        # the noise only matters where the tanh profile is not saturated
+        # (tanh(x) rounds to +-1 in double precision beyond |x| ~ 19.1)
+        rb, (bx, by, bz) = np.broadcast_arrays(r, rx, ry, rz)[0], np.broadcast_arrays(rx, ry, rz)
+        near = np.abs(rb - radius) < radius * noise + 20.0 * smear_cells * max(spec.dx)
+        theta = np.arccos(np.clip(bz[near] / np.maximum(rb[near], 1e-300), -1.0, 1.0))
+        phi = np.arctan2(by[near], bx[near])
+        R = np.full(rb.shape, radius)
+        R[near] = radius * (1.0 + noise * _real_sph_harm_sum(theta, phi, coeffs, lmax) / smax)
     else:
         R = radius
     H = _smooth_step(r - R, smear_cells * spec.dx[0])
