@@ -209,6 +209,27 @@ def test_nonphysical_state_is_reported():
 
 
 @pytest.mark.parametrize("kernel", sorted(KERNELS))
+def test_nonphysical_flag_agrees_with_oracle(kernel):
+    """An under-resolved bubble (about 2 cells per radius in z) whose WENO
+    reconstructions leave the physical range in the first step: the oracle and
+    the GPU both report it; a resolved one is clean on both."""
+    for n, expect in (((24, 20, 18), True), ((36, 34, 33), False)):
+        spec, w = W.bubble_collapse_3d(n=n)
+        say(f"[flag] bubble {n} kernel={kernel}")
+        _, _, st = oracle.run(spec, oracle.prim_to_cons_field(spec, w), 1, cfl=0.3)
+        assert (st == oracle.E_NONPHYSICAL) == expect
+        s = mfc.Solver(spec, kernel=KERNELS[kernel])
+        q = gpu_state(s, w)
+        s.step(q, cfl=0.3)
+        if expect:
+            with pytest.raises(mfc.MfcError) as e:
+                s.check()
+            assert e.value.status == mfc.MFC_E_NONPHYSICAL
+        else:
+            s.check()
+
+
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
 def test_deterministic_reruns(kernel):
     spec, w = W.bubble_collapse_3d(n=(37, 21, 19))
     outs = []
