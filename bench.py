@@ -5,16 +5,18 @@
 Workload: the 3D air-bubble collapse in water on 128^3 cells (7 state
 variables, FP64, CFL 0.3, seeded spherical-harmonic surface noise), state
 resident in HBM.  A step is one full SSP-RK3 step: ghost fill, the CFL
-wave-speed reduction and three fused right-hand-side launches.  The metric
-is RHS cell-updates/s = interior cells x 3 stages x steps / wall time.
+wave-speed reduction and three right-hand-side evaluations, each with its
+stage update.  The metric is RHS cell-updates/s = interior cells x 3 stages
+x steps / wall time.
 
 One JSON line is printed.  `roofline` is measured on the dominant kernel (the
-fused right-hand side) with HIP events recorded by the library around every
-launch of it on the launch stream during the timed region.  `cpu_baseline`
-times the FP64 CPU oracle on the host for one SSP-RK3 step of the same
-workload.
+x+y kernel of the split path, or the single fused kernel) with HIP events
+recorded by the library around every launch of it on the launch stream
+during the timed region; `roofline_second_kernel` does the same for the z +
+stage-update kernel of the split path.  `cpu_baseline` times the FP64 CPU
+oracle on the host for one SSP-RK3 step of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--n 128] [--kernel fused|staged]
+    python bench.py [--steps K] [--warmup W] [--n 128] [--kernel split|fused|staged]
 """
 import argparse
 import json
@@ -37,6 +39,15 @@ FLOPS_PER_CELL_UPDATE = 2416
 # read the stage input (56 B), read q^n on stages 2 and 3 (56 B), write the
 # result (56 B): (112 + 168 + 168) / 3.
 BYTES_PER_CELL_UPDATE = (112 + 168 + 168) / 3
+# The split path's two kernels.  x+y kernel: conservative->primitive 28,
+# WENO5 88 x 7 x 2 = 1232, HLLC 146 x 2 = 292, x+y flux differences and
+# divergence 49 -> 1601 flops; reads the stage input (56 B) and writes the
+# x+y part (8 values, 64 B).  z kernel: the remaining 2416 - 1601 = 815 flops;
+# reads the stage input, the x+y part and q^n on stages 2-3, writes the
+# result: 56 + 64 + 56 * 2/3 + 56 B.
+SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences)", flops=1601, bytes=56 + 64),
+         1: dict(name="k_z (z reconstruction, HLLC, source, stage update)", flops=2416 - 1601,
+                 bytes=56 + 64 + 56 * 2 / 3 + 56)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_HBM = 8.0e12
 
@@ -61,7 +72,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--kernel", choices=["fused", "staged"], default="fused")
+    ap.add_argument("--kernel", choices=["fused", "staged", "split"], default="split")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -77,7 +88,7 @@ def main():
 
     torch.cuda.set_device(0)
     spec, w = W.bubble_collapse_3d(n=args.n)
-    kernel = mfc.MFC_KERNEL_FUSED if args.kernel == "fused" else mfc.MFC_KERNEL_STAGED
+    kernel = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}[args.kernel]
     solver = mfc.Solver(spec, kernel=kernel)
     q = solver.state_from_prim(w)
     cfl = 0.3
@@ -97,7 +108,8 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_kernel, launches = mfc.mfc_kernel_time(solver.h)
+    ms_kernel, launches = mfc.mfc_kernel_time(solver.h, 0)
+    ms_kernel1, launches1 = mfc.mfc_kernel_time(solver.h, 1)
     mfc.mfc_set_kernel_timing(solver.h, False)
     solver.check()
     ev_s = e0.elapsed_time(e1) / 1e3
@@ -105,17 +117,27 @@ def main():
 
     updates = spec.cells * 3 * args.steps
     value = updates / elapsed
-    avg_launch = ms_kernel / 1e3 / max(launches, 1)
-    flops_launch = FLOPS_PER_CELL_UPDATE * spec.cells
-    bytes_launch = BYTES_PER_CELL_UPDATE * spec.cells
-    achieved = flops_launch / avg_launch
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-            "kernel": "k_fused<3> (fused RHS + stage update)", "launches": launches,
-            "avg_launch_us": avg_launch * 1e6,
-            "flops_per_cell_update": FLOPS_PER_CELL_UPDATE,
-            "hbm_algorithmic_GBps": bytes_launch / avg_launch / 1e9,
-            "hbm_frac": bytes_launch / avg_launch / PEAK_HBM}
+    def roofline(ms, n, name, flops, nbytes):
+        avg = ms / 1e3 / max(n, 1)
+        achieved = flops * spec.cells / avg
+        hbm = nbytes * spec.cells / avg
+        bound = "alu" if flops / nbytes > PEAK_FP64_VALU / PEAK_HBM else "hbm"
+        r = {"bound": bound, "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+             "frac": achieved / PEAK_FP64_VALU, "traffic": None}
+        if bound == "hbm":
+            r.update(achieved=hbm / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=hbm / PEAK_HBM)
+        r.update({"kernel": name, "launches": n, "avg_launch_us": avg * 1e6, "flops_per_cell_update": flops,
+                  "bytes_per_cell_update": nbytes, "fp64_TFLOPs": achieved / 1e12, "fp64_frac": achieved / PEAK_FP64_VALU,
+                  "hbm_algorithmic_GBps": hbm / 1e9, "hbm_frac": hbm / PEAK_HBM})
+        return r
+
+    if args.kernel == "split":
+        roof = roofline(ms_kernel, launches, SPLIT[0]["name"], SPLIT[0]["flops"], SPLIT[0]["bytes"])
+        roof_z = roofline(ms_kernel1, launches1, SPLIT[1]["name"], SPLIT[1]["flops"], SPLIT[1]["bytes"])
+    else:
+        name = "k_fused<3> (fused RHS + stage update)" if args.kernel == "fused" else "staged RHS sequence"
+        roof = roofline(ms_kernel, launches, name, FLOPS_PER_CELL_UPDATE, BYTES_PER_CELL_UPDATE)
+        roof_z = None
     t, _ = solver.time()
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
@@ -124,6 +146,8 @@ def main():
                       "cfl": cfl, "precision": "fp64", "kernel": args.kernel, "recon": "weno5",
                       "parallelism": "single GPU"},
            "roofline": roof, "simulated_time_s": t}
+    if roof_z:
+        out["roofline_second_kernel"] = roof_z
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, w)
     print(json.dumps(out), flush=True)

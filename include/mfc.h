@@ -62,8 +62,9 @@ enum { MFC_RECON_WENO5 = 0, MFC_RECON_LEARNED = 1 };
 
 /* Kernel implementation of the right-hand side. */
 enum {
-    MFC_KERNEL_FUSED = 0,   /* one fused pass per stage (default)               */
-    MFC_KERNEL_STAGED = 1   /* separate reconstruction / Riemann / update passes */
+    MFC_KERNEL_FUSED = 0,   /* one fused pass per stage (default)                    */
+    MFC_KERNEL_STAGED = 1,  /* separate reconstruction / Riemann / update passes      */
+    MFC_KERNEL_SPLIT = 2    /* 3D: an x+y pass and a z + stage-update pass per stage  */
 };
 
 typedef struct mfc_grid mfc_grid;
@@ -143,12 +144,15 @@ int mfc_reset_time(mfc_grid *g, void *stream);
  * non-physical cell since the last check, and clear the flag. */
 int mfc_check(mfc_grid *g, void *stream);
 
-/* Kernel timing: while enabled, every launch of the right-hand-side kernel
- * (the dominant kernel) is bracketed by HIP events on the launch stream.
- * mfc_kernel_time synchronises, returns the summed duration (ms) and number
- * of launches since the last call, and resets both. */
+/* Kernel timing: while enabled, every launch of the right-hand-side kernels
+ * is bracketed by HIP events on the launch stream.  Slot 0 is the main
+ * right-hand-side kernel (the fused kernel, the x+y kernel of the split
+ * path, or the whole staged sequence); slot 1 is the z + stage-update kernel
+ * of the split path.  mfc_kernel_time synchronises, returns the summed
+ * duration (ms) and number of launches of that slot since the last call for
+ * it, and resets them.  slot outside [0, 1] gives MFC_E_ARG. */
 int mfc_set_kernel_timing(mfc_grid *g, int enable);
-int mfc_kernel_time(mfc_grid *g, double *ms_total, int64_t *launches);
+int mfc_kernel_time(mfc_grid *g, int slot, double *ms_total, int64_t *launches);
 
 /* Message for a status code (static storage). */
 const char *mfc_strerror(int status);

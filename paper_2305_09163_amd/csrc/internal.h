@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,7 @@ struct mfc_grid {
     int64_t cells_padded;  // px * py * pz
     int64_t cells;         // interior cells
     int device;
+    int cu_count;          // compute units of the device (resident-workgroup sizing)
 
     // scratch owned by the handle (device memory)
     void *stage_a = nullptr;   // RK stage state q^(1)
@@ -25,14 +27,15 @@ struct mfc_grid {
     double *recp = nullptr;    // staged path: reconstruction at x_{i+1/2}, per cell
     double *recm = nullptr;    // staged path: reconstruction at x_{i-1/2}, per cell
     double *faces = nullptr;   // staged path: 3 directions x (nvar + 1) face arrays
+    double *lxy = nullptr;     // split path: x+y flux differences and div(u), nvar + 1 arrays
     double *partial = nullptr; // per-block maxima of the wave-speed reduction
     double *scalars = nullptr; // [0] smax, [1] dt, [2] t, [3] spare
     int *flag = nullptr;       // non-physical flag
 
-    // kernel timing
+    // kernel timing, per slot (0: main right-hand-side kernel, 1: z kernel)
     bool timing = false;
-    std::vector<hipEvent_t> ev;  // pairs (start, stop)
-    size_t ev_used = 0;
+    std::vector<hipEvent_t> ev[2];  // pairs (start, stop)
+    size_t ev_used[2] = {0, 0};
 };
 
 namespace mfc {
@@ -45,8 +48,8 @@ int fail(int status, const std::string &detail);
 int hip_status(hipError_t e, const char *what);
 
 // kernel timing: bracket one launch of the dominant kernel
-void timing_begin(mfc_grid *h, hipStream_t s);
-void timing_end(mfc_grid *h, hipStream_t s);
+void timing_begin(mfc_grid *h, hipStream_t s, int slot = 0);
+void timing_end(mfc_grid *h, hipStream_t s, int slot = 0);
 
 // Launchers.  `q` has ghosts filled.  mode 0: out = rhs; mode s = 1, 2, 3:
 // out = a_s q0 + b_s (q + dt rhs) with the SSP-RK3 stage coefficients.
@@ -54,6 +57,8 @@ void timing_end(mfc_grid *h, hipStream_t s);
 int launch_rhs_staged(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
                       const double *dt_dev, hipStream_t s);
 int launch_rhs_fused(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+                     const double *dt_dev, hipStream_t s);
+int launch_rhs_split(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
                      const double *dt_dev, hipStream_t s);
 
 }  // namespace mfc

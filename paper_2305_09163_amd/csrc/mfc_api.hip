@@ -26,24 +26,25 @@ int hip_status(hipError_t e, const char *what)
                 std::string(what) + ": " + hipGetErrorString(e));
 }
 
-void timing_begin(mfc_grid *h, hipStream_t s)
+void timing_begin(mfc_grid *h, hipStream_t s, int slot)
 {
     if (!h->timing) return;
-    if (h->ev_used + 2 > h->ev.size()) {
+    auto &ev = h->ev[slot];
+    if (h->ev_used[slot] + 2 > ev.size()) {
         for (int t = 0; t < 64; t++) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return;
-            h->ev.push_back(e);
+            ev.push_back(e);
         }
     }
-    (void)hipEventRecord(h->ev[h->ev_used], s);
+    (void)hipEventRecord(ev[h->ev_used[slot]], s);
 }
 
-void timing_end(mfc_grid *h, hipStream_t s)
+void timing_end(mfc_grid *h, hipStream_t s, int slot)
 {
-    if (!h->timing || h->ev_used + 2 > h->ev.size()) return;
-    (void)hipEventRecord(h->ev[h->ev_used + 1], s);
-    h->ev_used += 2;
+    if (!h->timing || h->ev_used[slot] + 2 > h->ev[slot].size()) return;
+    (void)hipEventRecord(h->ev[slot][h->ev_used[slot] + 1], s);
+    h->ev_used[slot] += 2;
 }
 
 namespace {
@@ -217,7 +218,8 @@ int validate(const mfc_grid_desc *d)
     if (!(d->weno_eps > 0.0)) return fail(MFC_E_ARG, "weno_eps must be > 0");
     if (d->precision != MFC_FP64 && d->precision != MFC_FP32_MIXED) return fail(MFC_E_ARG, "unknown precision");
     if (d->recon != MFC_RECON_WENO5 && d->recon != MFC_RECON_LEARNED) return fail(MFC_E_ARG, "unknown recon");
-    if (d->kernel != MFC_KERNEL_FUSED && d->kernel != MFC_KERNEL_STAGED) return fail(MFC_E_ARG, "unknown kernel");
+    if (d->kernel != MFC_KERNEL_FUSED && d->kernel != MFC_KERNEL_STAGED && d->kernel != MFC_KERNEL_SPLIT)
+        return fail(MFC_E_ARG, "unknown kernel");
     if (d->precision != MFC_FP64) return fail(MFC_E_UNSUPPORTED, "only MFC_FP64 is built in this version");
     if (d->recon != MFC_RECON_WENO5) return fail(MFC_E_UNSUPPORTED, "only MFC_RECON_WENO5 is built in this version");
     return MFC_OK;
@@ -247,6 +249,7 @@ int rhs_dispatch(mfc_grid *h, const double *q, const double *q0, double *out, in
                  const double *dt_dev, hipStream_t s)
 {
     if (h->desc.kernel == MFC_KERNEL_STAGED) return launch_rhs_staged(h, q, q0, out, mode, dt, dt_dev, s);
+    if (h->desc.kernel == MFC_KERNEL_SPLIT) return launch_rhs_split(h, q, q0, out, mode, dt, dt_dev, s);
     return launch_rhs_fused(h, q, q0, out, mode, dt, dt_dev, s);
 }
 
@@ -301,9 +304,10 @@ int mfc_free_grid(mfc_grid *h)
     if (!h) return MFC_OK;
     (void)hipDeviceSynchronize();
     for (void *p : {(void *)h->stage_a, (void *)h->stage_b, (void *)h->prim, (void *)h->recp, (void *)h->recm,
-                    (void *)h->faces, (void *)h->partial, (void *)h->scalars, (void *)h->flag})
+                    (void *)h->faces, (void *)h->lxy, (void *)h->partial, (void *)h->scalars, (void *)h->flag})
         if (p) (void)hipFree(p);
-    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    for (auto &ev : h->ev)
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     delete h;
     return MFC_OK;
 }
@@ -344,9 +348,11 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
     g.eps = desc->weno_eps;
     h->cells_padded = g.vstride;
     h->cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    if (hipGetDevice(&h->device) != hipSuccess) {
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess ||
+        h->cu_count <= 0) {
         delete h;
-        return fail(MFC_E_HIP, "hipGetDevice failed");
+        return fail(MFC_E_HIP, "device query failed");
     }
 
     int64_t sb = state_bytes(h);
@@ -362,6 +368,8 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
         alloc((void **)&h->recm, sb);
         alloc((void **)&h->faces, (int64_t)3 * (h->nvar + 1) * h->cells_padded * 8);
     }
+    if (desc->kernel == MFC_KERNEL_SPLIT && desc->ndim == 3)
+        alloc((void **)&h->lxy, (int64_t)(h->nvar + 1) * h->cells_padded * 8);
     alloc((void **)&h->partial, kReduceBlocks * 8);
     alloc((void **)&h->scalars, 4 * 8);
     alloc((void **)&h->flag, 8);
@@ -546,25 +554,27 @@ int mfc_set_kernel_timing(mfc_grid *h, int enable)
 {
     if (bad_handle(h)) return fail(MFC_E_ARG, "handle is NULL");
     h->timing = enable != 0;
-    h->ev_used = 0;
+    h->ev_used[0] = h->ev_used[1] = 0;
     return MFC_OK;
 }
 
-int mfc_kernel_time(mfc_grid *h, double *ms_total, int64_t *launches)
+int mfc_kernel_time(mfc_grid *h, int slot, double *ms_total, int64_t *launches)
 {
     if (bad_handle(h) || !ms_total || !launches) return fail(MFC_E_ARG, "null argument");
+    if (slot < 0 || slot > 1) return fail(MFC_E_ARG, "slot must be 0 or 1");
+    const auto &ev = h->ev[slot];
     double total = 0.0;
-    for (size_t p = 0; p + 1 < h->ev_used; p += 2) {
-        hipError_t e = hipEventSynchronize(h->ev[p + 1]);
+    for (size_t p = 0; p + 1 < h->ev_used[slot]; p += 2) {
+        hipError_t e = hipEventSynchronize(ev[p + 1]);
         if (e != hipSuccess) return hip_status(e, "event sync");
         float ms = 0.f;
-        e = hipEventElapsedTime(&ms, h->ev[p], h->ev[p + 1]);
+        e = hipEventElapsedTime(&ms, ev[p], ev[p + 1]);
         if (e != hipSuccess) return hip_status(e, "event elapsed time");
         total += ms;
     }
     *ms_total = total;
-    *launches = (int64_t)(h->ev_used / 2);
-    h->ev_used = 0;
+    *launches = (int64_t)(h->ev_used[slot] / 2);
+    h->ev_used[slot] = 0;
     return MFC_OK;
 }
 

@@ -54,7 +54,7 @@ __device__ __forceinline__ void mixture(const Grid &g, double a1, double &Gam, d
 // Frozen mixture sound speed squared, c^2 = ((Gamma + 1) p + Pi) / (Gamma rho).
 __device__ __forceinline__ double sound2(double Gam, double Pi, double rho, double p)
 {
-    return ((Gam + 1.0) * p + Pi) / (Gam * rho);
+    return __builtin_fma(Gam + 1.0, p, Pi) * rcp(Gam * rho);
 }
 
 __device__ __forceinline__ bool nonphysical(double rho, double c2)
@@ -68,7 +68,7 @@ __device__ __forceinline__ bool cons_to_prim(const Grid &g, const double *q, dou
 {
     constexpr int E = 2 + NDIM, A = 3 + NDIM;
     double rho = q[0] + q[1];
-    double ir = 1.0 / rho;
+    double ir = rcp(rho);
     double Gam, Pi;
     mixture(g, q[A], Gam, Pi);
     double ke = 0.0;
@@ -79,9 +79,13 @@ __device__ __forceinline__ bool cons_to_prim(const Grid &g, const double *q, dou
         w[2 + m] = q[2 + m] * ir;
         ke += q[2 + m] * w[2 + m];
     }
-    w[E] = (q[E] - 0.5 * ke - Pi) / Gam;
+    const double iG = rcp(Gam);
+    w[E] = (q[E] - 0.5 * ke - Pi) * iG;
     w[A] = q[A];
-    return nonphysical(rho, sound2(Gam, Pi, rho, w[E]));
+    // c^2 = ((Gamma + 1) p + Pi) / (Gamma rho): its sign and finiteness
+    // without the division
+    const double num = __builtin_fma(Gam + 1.0, w[E], Pi);
+    return !(rho > 0.0) || !(num * iG > 0.0) || !__builtin_isfinite(rho) || !__builtin_isfinite(num * iG * ir);
 }
 
 template <int NDIM>
@@ -107,36 +111,39 @@ __device__ __forceinline__ void prim_to_cons(const Grid &g, const double *w, dou
 // Both reconstructions a cell contributes, from its 5-cell stencil
 // (vm2, vm1, v0, vp1, vp2): `plus` at its right face x_{i+1/2} (the left
 // state of that face) and `minus` at its left face x_{i-1/2}.  The two share
-// the divided differences and the smoothness indicators.  The nonlinear
-// weights a_r = d_r/(eps + beta_r)^2 are normalised through common
-// denominators, a_r ~ d_r prod_{s != r} (eps + beta_s)^2, so that one
-// reciprocal serves both faces; the result is written as v0 plus a weighted
-// sum of candidate increments, which reproduces constants exactly.
+// the divided differences a = v0 - vm1, b = vm1 - vm2, c = vp1 - v0,
+// d = vp2 - vp1 and the smoothness indicators.
+//
+// Arithmetic, equal to the Jiang-Shu definitions up to rounding:
+//   - every smoothness indicator is scaled by 3, with eps scaled alike
+//     (3 beta_0 = a (10a - 11b) + 4b^2, 3 beta_1 = c (4c - 5a) + 4a^2,
+//     3 beta_2 = c (10c - 11d) + 4d^2); the weights depend only on ratios of
+//     (eps + beta_r)^2, so the common factor cancels;
+//   - a_r = d_r/(eps + beta_r)^2 is normalised through common denominators,
+//     a_r ~ d_r prod_{s != r} (eps + beta_s)^2, with the ideal weights scaled
+//     by 10 (1, 6, 3 and 3, 6, 1), so one reciprocal serves both faces;
+//   - the candidates enter as increments over v0 scaled by 6
+//     (6 (p_r - v0) at x_{i+1/2}: 5a - 2b, 2c + a, 4c - d; at x_{i-1/2}:
+//     b - 4a, -(2a + c), 2d - 5c), which reproduces constants exactly.
 __device__ __forceinline__ void weno5_pair(double vm2, double vm1, double v0, double vp1, double vp2,
                                            double eps, double &plus, double &minus)
 {
-    const double dm2 = vm1 - vm2, dm1 = v0 - vm1, d0 = vp1 - v0, d1 = vp2 - vp1;
-    const double b0 = (10.0 / 3.0) * dm1 * dm1 - (11.0 / 3.0) * dm1 * dm2 + (4.0 / 3.0) * dm2 * dm2;
-    const double b1 = (4.0 / 3.0) * d0 * d0 - (5.0 / 3.0) * d0 * dm1 + (4.0 / 3.0) * dm1 * dm1;
-    const double b2 = (10.0 / 3.0) * d0 * d0 - (11.0 / 3.0) * d0 * d1 + (4.0 / 3.0) * d1 * d1;
-    const double e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
+    const double b = vm1 - vm2, a = v0 - vm1, c = vp1 - v0, d = vp2 - vp1;
+    const double e3 = 3.0 * eps;
+    const double e0 = __builtin_fma(a, __builtin_fma(10.0, a, -11.0 * b), __builtin_fma(4.0 * b, b, e3));
+    const double e1 = __builtin_fma(c, __builtin_fma(4.0, c, -5.0 * a), __builtin_fma(4.0 * a, a, e3));
+    const double e2 = __builtin_fma(c, __builtin_fma(10.0, c, -11.0 * d), __builtin_fma(4.0 * d, d, e3));
     const double s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
-    const double m0 = s1 * s2, m1 = s0 * s2, m2 = s0 * s1;
-    // candidate increments at x_{i+1/2} and x_{i-1/2}
-    const double cp0 = (5.0 / 6.0) * dm1 - (1.0 / 3.0) * dm2;
-    const double cp1 = (1.0 / 3.0) * d0 + (1.0 / 6.0) * dm1;
-    const double cp2 = (2.0 / 3.0) * d0 - (1.0 / 6.0) * d1;
-    const double cm0 = (1.0 / 6.0) * dm2 - (2.0 / 3.0) * dm1;
-    const double cm1 = -(1.0 / 3.0) * dm1 - (1.0 / 6.0) * d0;
-    const double cm2 = (1.0 / 3.0) * d1 - (5.0 / 6.0) * d0;
-    const double ap0 = 0.1 * m0, ap1 = 0.6 * m1, ap2 = 0.3 * m2;
-    const double am0 = 0.3 * m0, am1 = 0.6 * m1, am2 = 0.1 * m2;
-    const double sp = ap0 + ap1 + ap2, sm = am0 + am1 + am2;
-    const double np = ap0 * cp0 + ap1 * cp1 + ap2 * cp2;
-    const double nm = am0 * cm0 + am1 * cm1 + am2 * cm2;
-    const double r = rcp(sp * sm);
-    plus = v0 + np * (sm * r);
-    minus = v0 + nm * (sp * r);
+    const double m0 = s1 * s2, m1 = 6.0 * (s0 * s2), m2 = s0 * s1;  // m1 carries the ideal weight 6
+    const double sp = __builtin_fma(3.0, m2, m0 + m1);                // weights 1, 6, 3
+    const double sm = __builtin_fma(3.0, m0, m1 + m2);                // weights 3, 6, 1
+    const double np = __builtin_fma(3.0 * m2, __builtin_fma(4.0, c, -d),
+                                    __builtin_fma(m1, __builtin_fma(2.0, c, a), m0 * __builtin_fma(5.0, a, -2.0 * b)));
+    const double nm = __builtin_fma(m2, __builtin_fma(2.0, d, -5.0 * c),
+                                    __builtin_fma(m1, -__builtin_fma(2.0, a, c), 3.0 * m0 * __builtin_fma(-4.0, a, b)));
+    const double r = rcp(6.0 * (sp * sm));
+    plus = __builtin_fma(np, sm * r, v0);
+    minus = __builtin_fma(nm, sp * r, v0);
 }
 
 // ------------------------------------------------------------------- HLLC
@@ -164,7 +171,7 @@ __device__ __forceinline__ bool hllc(const Grid &g, const double *wL, const doub
     const double sL = __builtin_fmin(uL - cL, uR - cR);
     const double sR = __builtin_fmax(uL + cL, uR + cR);
     const double mL = rhoL * (sL - uL), mR = rhoR * (sR - uR);
-    const double sS = (pR - pL + mL * uL - mR * uR) / (mL - mR);
+    const double sS = (pR - pL + mL * uL - mR * uR) * rcp(mL - mR);
 
     const bool super_L = sL >= 0.0, super_R = sR <= 0.0;
     const bool useL = super_L || (!super_R && sS >= 0.0);
@@ -192,7 +199,7 @@ __device__ __forceinline__ bool hllc(const Grid &g, const double *wL, const doub
 
     // star correction s_K (q*_K - q_K), with xi - 1 = (s* - u)/(s_K - s*)
     const double sku = sK - un;
-    const double ism = 1.0 / (sK - sS);
+    const double ism = rcp(sK - sS);
     const double xim1 = (sS - un) * ism;
     const double xi = sku * ism;
     double dq[NV - 1];
@@ -200,7 +207,8 @@ __device__ __forceinline__ bool hllc(const Grid &g, const double *wL, const doub
     dq[1] = xim1 * w[1];
 #pragma unroll
     for (int m = 0; m < NDIM; m++) dq[2 + m] = (m == DIR) ? rho * (xi * sS - un) : xim1 * rho * w[2 + m];
-    dq[E] = xim1 * En + xi * (sS - un) * (rho * sS + p / sku);
+    // xi (s* - u)(rho s* + p/(s_K - u)) = (s* - u)(xi rho s* + p/(s_K - s*))
+    dq[E] = xim1 * En + (sS - un) * __builtin_fma(xi * rho, sS, p * ism);
 #pragma unroll
     for (int v = 0; v < NV - 1; v++) F[v] = star ? F[v] + sK * dq[v] : F[v];
 

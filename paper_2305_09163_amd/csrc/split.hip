@@ -1,0 +1,255 @@
+// Split right-hand side (3D): two launches per Runge-Kutta stage.
+//
+//   k_xy  x and y directions of eq. (fvmdis) (Sec. 3.1): a workgroup of
+//         16 x 16 threads owns a 16 x 16 tile of one plane; the plane (with
+//         3-cell halos) is converted to primitives into LDS once, every cell
+//         of the tile plus one halo cell per side is reconstructed once per
+//         direction (WENO5, both face values from one stencil, Sec. 3.2), the
+//         HLLC flux of every face (Sec. 3.2.1) is computed once and shared by
+//         the two cells of the face.  It writes the x+y flux differences and
+//         the x+y face-velocity divergence of every cell (8 values).
+//   k_z   z direction plus the stage update: one thread per (x, y) column
+//         marches through a chunk of planes with the primitives of five
+//         planes in registers, reconstructs each cell once (both faces) and
+//         solves each z face once, adds the x+y part, forms the alpha1 div(u)
+//         source and the SSP-RK3 combination and writes the stage result.
+//
+// Neither kernel carries the other's state, so each fits its registers
+// without spilling; the price is one 64-byte round trip per cell through HBM.
+#include "internal.h"
+
+namespace mfc {
+namespace {
+
+constexpr int TX = 16, TY = 16, NT = TX * TY;
+constexpr int PX = TX + 2 * NG, PY = TY + 2 * NG;
+constexpr int NPX = (TX + 2) * TY, NFX = (TX + 1) * TY;
+constexpr int NPY = TX * (TY + 2), NFY = TX * (TY + 1);
+constexpr int NP = NPX > NPY ? NPX : NPY;
+constexpr int NF = NFX > NFY ? NFX : NFY;
+constexpr int NHALO = 2 * NG * (TX + TY);
+constexpr int kPlanesXY = 8;    // planes per k_xy workgroup
+constexpr int kZX = 64, kZY = 4;  // k_z workgroup: 64 x 4 columns
+constexpr int kLZ = 16;          // planes per k_z workgroup
+
+__device__ __forceinline__ int64_t offset(const Grid &g, int i, int j, int k)
+{
+    return (int64_t)(k + g.off[2]) * g.stride[2] + (int64_t)(j + g.off[1]) * g.stride[1] + (i + g.off[0]);
+}
+
+// Load and convert one cell; flag only cells the method reads (at most one
+// coordinate outside the interior: out-of-grid lanes of ragged tiles may
+// touch never-written edge ghosts whose results are discarded).
+__device__ __forceinline__ bool load_prim3(const Grid &g, const double *__restrict__ q, int i, int j, int k, double *w)
+{
+    constexpr int NV = 7;
+    const int64_t c = offset(g, i, j, k);
+    double qc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
+    const bool bad = cons_to_prim<3>(g, qc, w);
+    const int outside = (i < 0 || i >= g.n[0]) + (j < 0 || j >= g.n[1]) + (k < 0 || k >= g.n[2]);
+    return bad && outside <= 1;
+}
+
+__global__ void __launch_bounds__(NT, 2)
+    k_xy(Grid g, const double *__restrict__ q, double *__restrict__ lxy, int *__restrict__ flag)
+{
+    constexpr int NV = 7;
+    __shared__ double s_plane[NV][PY][PX];
+    __shared__ double s_pair[2 * NV][NP];
+    __shared__ double s_flux[NV + 1][NF];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int z0 = blockIdx.z * kPlanesXY, z1 = min(z0 + kPlanesXY, g.n[2]);
+    const int xmax = g.n[0] + NG - 1, ymax = g.n[1] + NG - 1;
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool own = gx < g.n[0] && gy < g.n[1];
+    bool bad = false;
+
+    for (int k = z0; k < z1; k++) {
+        // ---- plane k (own cell + x/y halos) into LDS as primitives
+        {
+            double w[NV];
+            bad |= load_prim3(g, q, min(gx, xmax), min(gy, ymax), k, w);
+#pragma unroll
+            for (int v = 0; v < NV; v++) s_plane[v][ty + NG][tx + NG] = w[v];
+        }
+        for (int h = tid; h < NHALO; h += NT) {
+            int li, lj;
+            if (h < 2 * NG * TY) {
+                const int c = h % (2 * NG), row = h / (2 * NG);
+                li = c < NG ? c : TX + c;
+                lj = row + NG;
+            } else {
+                const int h2 = h - 2 * NG * TY;
+                const int c = h2 % TX, r = h2 / TX;
+                li = c + NG;
+                lj = r < NG ? r : TY + r;
+            }
+            double w[NV];
+            bad |= load_prim3(g, q, min(x0 + li - NG, xmax), min(y0 + lj - NG, ymax), k, w);
+#pragma unroll
+            for (int v = 0; v < NV; v++) s_plane[v][lj][li] = w[v];
+        }
+        __syncthreads();
+
+        // ---- x: reconstruct cells -1 .. TX of every row, then the faces
+        for (int p = tid; p < NPX; p += NT) {
+            const int row = p / (TX + 2), c = p % (TX + 2);
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const double *s = &s_plane[v][row + NG][c];
+                weno5_pair(s[0], s[1], s[2], s[3], s[4], g.eps, s_pair[v][p], s_pair[NV + v][p]);
+            }
+        }
+        __syncthreads();
+        for (int f = tid; f < NFX; f += NT) {
+            const int row = f / (TX + 1), fi = f % (TX + 1);
+            const int pl = row * (TX + 2) + fi;
+            double wL[NV], wR[NV], F[NV], uf;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                wL[v] = s_pair[v][pl];
+                wR[v] = s_pair[NV + v][pl + 1];
+            }
+            const bool b = hllc<3, 0>(g, wL, wR, F, uf);
+            bad |= b && (y0 + row < g.n[1]) && (x0 + fi <= g.n[0]);
+#pragma unroll
+            for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
+            s_flux[NV][f] = uf;
+        }
+        __syncthreads();
+        double L[NV], divu;
+        {
+            const int f = ty * (TX + 1) + tx;
+#pragma unroll
+            for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * g.inv_dx[0];
+            divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * g.inv_dx[0];
+        }
+        // ---- y: reconstruct rows -1 .. TY of every column, then the faces
+        for (int p = tid; p < NPY; p += NT) {
+            const int c = p % TX, r = p / TX;
+            const int li = c + NG;
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li], s_plane[v][r + 3][li],
+                           s_plane[v][r + 4][li], g.eps, s_pair[v][p], s_pair[NV + v][p]);
+        }
+        __syncthreads();
+        for (int f = tid; f < NFY; f += NT) {
+            const int c = f % TX, fr = f / TX;
+            const int pl = fr * TX + c;
+            double wL[NV], wR[NV], F[NV], uf;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                wL[v] = s_pair[v][pl];
+                wR[v] = s_pair[NV + v][pl + TX];
+            }
+            const bool b = hllc<3, 1>(g, wL, wR, F, uf);
+            bad |= b && (x0 + c < g.n[0]) && (y0 + fr <= g.n[1]);
+#pragma unroll
+            for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
+            s_flux[NV][f] = uf;
+        }
+        __syncthreads();
+        {
+            const int f = ty * TX + tx;
+#pragma unroll
+            for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * g.inv_dx[1];
+            divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * g.inv_dx[1];
+        }
+        if (own) {
+            const int64_t c = offset(g, gx, gy, k);
+#pragma unroll
+            for (int v = 0; v < NV; v++) lxy[v * g.vstride + c] = L[v];
+            lxy[NV * g.vstride + c] = divu;
+        }
+        // the next plane overwrites s_plane (last read before the y-face
+        // barrier) and s_pair/s_flux only after two more barriers
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+// z direction + stage update.  Threads of a workgroup own a 64 x 4 block of
+// columns (64 consecutive x per wavefront: coalesced plane loads) and march
+// through kLZ planes, starting two planes early to reconstruct cell z0-1 and
+// solve face z0-1/2 without writing.
+__global__ void __launch_bounds__(kZX * kZY, 2)
+    k_z(Grid g, const double *__restrict__ q, const double *q0, double *out, const double *__restrict__ lxy,
+        int mode, double dt, const double *__restrict__ dt_dev, int *__restrict__ flag)
+{
+    constexpr int NV = 7, A = 6;
+    const int gx = blockIdx.x * kZX + threadIdx.x % kZX;
+    const int gy = blockIdx.y * kZY + threadIdx.x / kZX;
+    if (gx >= g.n[0] || gy >= g.n[1]) return;   // no barriers in this kernel
+    const int z0 = blockIdx.z * kLZ, z1 = min(z0 + kLZ, g.n[2]);
+    const double hdt = mode ? (dt_dev ? *dt_dev : dt) : 0.0;
+    const double ca = mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0);
+    const double cb = mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0);
+    bool bad = false;
+
+    double zw[5][NV];   // primitives of planes k-1 .. k+3 after the shift
+    double pk[NV];      // cell k reconstructed at its + face
+    double Fz[NV + 1];  // flux and face velocity at k-1/2
+#pragma unroll
+    for (int p = 1; p < 5; p++) bad |= load_prim3(g, q, gx, gy, z0 - 4 + p, zw[p]);
+
+    for (int k = z0 - 2; k < z1; k++) {
+#pragma unroll
+        for (int p = 0; p < 4; p++)
+#pragma unroll
+            for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
+        bad |= load_prim3(g, q, gx, gy, k + 3, zw[4]);
+        double pn[NV], mn[NV], Fzn[NV + 1];
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], g.eps, pn[v], mn[v]);
+        if (k >= z0 - 1) bad |= hllc<3, 2>(g, pk, mn, Fzn, Fzn[NV]);
+#pragma unroll
+        for (int v = 0; v < NV; v++) pk[v] = pn[v];
+        if (k >= z0) {
+            const int64_t c = offset(g, gx, gy, k);
+            double L[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) L[v] = lxy[v * g.vstride + c] + (Fz[v] - Fzn[v]) * g.inv_dx[2];
+            const double divu = lxy[NV * g.vstride + c] + (Fzn[NV] - Fz[NV]) * g.inv_dx[2];
+            L[A] += zw[1][A] * divu;
+            if (mode == 0) {
+#pragma unroll
+                for (int v = 0; v < NV; v++) out[v * g.vstride + c] = L[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const int64_t o = v * g.vstride + c;
+                    out[o] = ca * q0[o] + cb * (q[o] + hdt * L[v]);
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v <= NV; v++) Fz[v] = Fzn[v];
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+int launch_rhs_split(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+                     const double *dt_dev, hipStream_t s)
+{
+    const Grid &g = h->g;
+    if (g.ndim != 3) return launch_rhs_fused(h, q, q0, out, mode, dt, dt_dev, s);
+    dim3 gxy((g.n[0] + TX - 1) / TX, (g.n[1] + TY - 1) / TY, (g.n[2] + kPlanesXY - 1) / kPlanesXY);
+    dim3 gz((g.n[0] + kZX - 1) / kZX, (g.n[1] + kZY - 1) / kZY, (g.n[2] + kLZ - 1) / kLZ);
+    timing_begin(h, s);
+    hipLaunchKernelGGL(k_xy, gxy, dim3(NT), 0, s, g, q, h->lxy, h->flag);
+    timing_end(h, s);
+    timing_begin(h, s, 1);
+    hipLaunchKernelGGL(k_z, gz, dim3(kZX * kZY), 0, s, g, q, q0, out, h->lxy, mode, dt, dt_dev, h->flag);
+    timing_end(h, s, 1);
+    return hip_status(hipGetLastError(), "split right-hand side launch");
+}
+
+}  // namespace mfc

@@ -12,7 +12,7 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmfc.so")
+LIB_PATH = os.environ.get("MFC_LIB") or os.path.join(HERE, "libmfc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mfc.h")
 
 MFC_OK = 0
@@ -24,7 +24,7 @@ MFC_E_UNSUPPORTED = -5
 MFC_BC_EXTRAP, MFC_BC_PERIODIC = 0, 1
 MFC_FP64, MFC_FP32_MIXED = 0, 1
 MFC_RECON_WENO5, MFC_RECON_LEARNED = 0, 1
-MFC_KERNEL_FUSED, MFC_KERNEL_STAGED = 0, 1
+MFC_KERNEL_FUSED, MFC_KERNEL_STAGED, MFC_KERNEL_SPLIT = 0, 1, 2
 
 
 class MfcError(RuntimeError):
@@ -58,7 +58,7 @@ _SIGNATURES = {
     "mfc_reset_time": [_VP, _VP],
     "mfc_check": [_VP, _VP],
     "mfc_set_kernel_timing": [_VP, ctypes.c_int],
-    "mfc_kernel_time": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "mfc_kernel_time": [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
 }
 
 
@@ -196,9 +196,9 @@ def mfc_set_kernel_timing(h, enable: bool):
     _check(lib().mfc_set_kernel_timing(h, int(enable)), "mfc_set_kernel_timing")
 
 
-def mfc_kernel_time(h):
+def mfc_kernel_time(h, slot: int = 0):
     ms, n = ctypes.c_double(), ctypes.c_int64()
-    _check(lib().mfc_kernel_time(h, ctypes.byref(ms), ctypes.byref(n)), "mfc_kernel_time")
+    _check(lib().mfc_kernel_time(h, slot, ctypes.byref(ms), ctypes.byref(n)), "mfc_kernel_time")
     return ms.value, n.value
 
 

@@ -14,7 +14,7 @@ from paper_2305_09163_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED}
+KERNELS = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}
 DEFAULT_KERNEL = mfc.MFC_KERNEL_FUSED
 
 
