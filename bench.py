@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--kernel", choices=["fused", "staged", "split"], default="split")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -89,7 +90,8 @@ def main():
     torch.cuda.set_device(0)
     spec, w = W.bubble_collapse_3d(n=args.n)
     kernel = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}[args.kernel]
-    solver = mfc.Solver(spec, kernel=kernel)
+    precision = mfc.MFC_FP64 if args.precision == "fp64" else mfc.MFC_FP32_MIXED
+    solver = mfc.Solver(spec, kernel=kernel, precision=precision)
     q = solver.state_from_prim(w)
     cfl = 0.3
     for _ in range(args.warmup):
@@ -141,9 +143,10 @@ def main():
     t, _ = solver.time()
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+           "data": "synthetic",
            "config": {"workload": f"bubble_collapse_3d_{args.n}", "cells": spec.cells, "nvar": spec.nvar,
-                      "cfl": cfl, "precision": "fp64", "kernel": args.kernel, "recon": "weno5",
+                      "cfl": cfl, "precision": args.precision, "kernel": args.kernel, "recon": "weno5",
                       "parallelism": "single GPU"},
            "roofline": roof, "simulated_time_s": t}
     if roof_z:

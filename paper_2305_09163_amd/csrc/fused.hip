@@ -47,30 +47,30 @@ constexpr int kLZ = 16;  // z planes per workgroup
 // may load edge/corner ghost cells, which are never written; their values
 // only feed lanes whose results are discarded, so they must not raise the
 // flag either.
-template <int NDIM>
-__device__ __forceinline__ bool load_prim(const Grid &g, const double *__restrict__ q, int i, int j, int k,
-                                          double *w)
+template <int NDIM, class T>
+__device__ __forceinline__ bool load_prim(const Grid &g, const T *__restrict__ q, int i, int j, int k, T *w)
 {
     constexpr int NV = 4 + NDIM;
     const int64_t c = (int64_t)(k + g.off[2]) * g.stride[2] + (int64_t)(j + g.off[1]) * g.stride[1] + (i + g.off[0]);
-    double qc[NV];
+    T qc[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
-    const bool bad = cons_to_prim<NDIM>(g, qc, w);
+    const bool bad = cons_to_prim<NDIM, T>(g, qc, w);
     const int outside = (i < 0 || i >= g.n[0]) + (j < 0 || j >= g.n[1]) + (k < 0 || k >= g.n[2]);
     return bad && outside <= 1;
 }
 
-template <int NDIM>
+template <int NDIM, class T>
 __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
-    k_fused(Grid g, const double *__restrict__ q, const double *q0, double *out, int mode, double dt,
+    k_fused(Grid g, const T *__restrict__ q, const T *q0, T *out, int mode, double dt,
             const double *__restrict__ dt_dev, int *__restrict__ flag, int lz)
 {
     using S = Shape<NDIM>;
     constexpr int NV = S::NV, A = 3 + NDIM, TX = S::TX, TY = S::TY, NT = S::NT, OY = S::OY;
-    __shared__ double s_plane[NV][S::PY][S::PX];
-    __shared__ double s_pair[2 * NV][S::NP];
-    __shared__ double s_flux[NV + 1][S::NF];
+    __shared__ T s_plane[NV][S::PY][S::PX];
+    __shared__ T s_pair[2 * NV][S::NP];
+    __shared__ T s_flux[NV + 1][S::NF];
+    const T eps = T(g.eps), idx = T(g.inv_dx[0]), idy = T(g.inv_dx[1]), idz = T(g.inv_dx[2]);
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -86,50 +86,50 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
 
     // ---- z march state (3D): primitives of planes k-1 .. k+3 of this column,
     // the reconstruction of cell k at its + face, the flux at face k-1/2.
-    double zw[5][NV];
-    double pk[NV];
-    double Fz[NV + 1];
+    T zw[5][NV];
+    T pk[NV];
+    T Fz[NV + 1];
     if constexpr (NDIM == 3) {
 #pragma unroll
-        for (int p = 0; p < 5; p++) bad |= load_prim<NDIM>(g, q, cx, cy, z0 - 3 + p, zw[p]);
-        double plus_prev[NV], mk[NV], dummy;
+        for (int p = 0; p < 5; p++) bad |= load_prim<NDIM, T>(g, q, cx, cy, z0 - 3 + p, zw[p]);
+        T plus_prev[NV], mk[NV], dummy;
 #pragma unroll
         for (int v = 0; v < NV; v++)
-            weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], g.eps, plus_prev[v], dummy);
+            weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, plus_prev[v], dummy);
 #pragma unroll
         for (int p = 0; p < 4; p++)
 #pragma unroll
             for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
-        bad |= load_prim<NDIM>(g, q, cx, cy, z0 + 2, zw[4]);
+        bad |= load_prim<NDIM, T>(g, q, cx, cy, z0 + 2, zw[4]);
 #pragma unroll
-        for (int v = 0; v < NV; v++) weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], g.eps, pk[v], mk[v]);
-        bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0)>(g, plus_prev, mk, Fz, Fz[NV]) && own;
+        for (int v = 0; v < NV; v++) weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, pk[v], mk[v]);
+        bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0), T>(g, plus_prev, mk, Fz, Fz[NV]) && own;
     }
 
-    const double hdt = mode ? (dt_dev ? *dt_dev : dt) : 0.0;
-    const double ca = mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0);
-    const double cb = mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0);
+    const T hdt = T(mode ? (dt_dev ? *dt_dev : dt) : 0.0);
+    const T ca = T(mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0));
+    const T cb = T(mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0));
 
     for (int k = z0; k < z1; k++) {
-        double wk[NV];
-        double Fzn[NV + 1];
+        T wk[NV];
+        T Fzn[NV + 1];
         if constexpr (NDIM == 3) {
 #pragma unroll
             for (int p = 0; p < 4; p++)
 #pragma unroll
                 for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
-            bad |= load_prim<NDIM>(g, q, cx, cy, k + 3, zw[4]);
-            double pn[NV], mn[NV];
+            bad |= load_prim<NDIM, T>(g, q, cx, cy, k + 3, zw[4]);
+            T pn[NV], mn[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
                 wk[v] = zw[1][v];
-                weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], g.eps, pn[v], mn[v]);
+                weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, pn[v], mn[v]);
             }
-            bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0)>(g, pk, mn, Fzn, Fzn[NV]) && own;
+            bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0), T>(g, pk, mn, Fzn, Fzn[NV]) && own;
 #pragma unroll
             for (int v = 0; v < NV; v++) pk[v] = pn[v];
         } else {
-            bad |= load_prim<NDIM>(g, q, cx, cy, 0, wk);
+            bad |= load_prim<NDIM, T>(g, q, cx, cy, 0, wk);
         }
 
         // ---- plane k into LDS: own cell, then the x and y halos
@@ -148,8 +148,8 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
                 lj = r < NG ? r : TY + r;
             }
             const int gi = min(x0 + li - NG, xmax), gj = min(y0 + lj - OY, ymax);
-            double w[NV];
-            bad |= load_prim<NDIM>(g, q, gi, gj, k, w);
+            T w[NV];
+            bad |= load_prim<NDIM, T>(g, q, gi, gj, k, w);
 #pragma unroll
             for (int v = 0; v < NV; v++) s_plane[v][lj][li] = w[v];
         }
@@ -161,8 +161,8 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
             const int lj = row + OY;
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                const double *s = &s_plane[v][lj][c];
-                weno5_pair(s[0], s[1], s[2], s[3], s[4], g.eps, s_pair[v][p], s_pair[NV + v][p]);
+                const T *s = &s_plane[v][lj][c];
+                weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
             }
         }
         __syncthreads();
@@ -170,25 +170,25 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
         for (int f = tid; f < S::NFX; f += NT) {
             const int row = f / (TX + 1), fi = f % (TX + 1);
             const int pl = row * (TX + 2) + fi;
-            double wL[NV], wR[NV], F[NV], uf;
+            T wL[NV], wR[NV], F[NV], uf;
 #pragma unroll
             for (int v = 0; v < NV; v++) {
                 wL[v] = s_pair[v][pl];
                 wR[v] = s_pair[NV + v][pl + 1];
             }
-            const bool b = hllc<NDIM, 0>(g, wL, wR, F, uf);
+            const bool b = hllc<NDIM, 0, T>(g, wL, wR, F, uf);
             bad |= b && (y0 + row < g.n[1]) && (x0 + fi <= g.n[0]);
 #pragma unroll
             for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
             s_flux[NV][f] = uf;
         }
         __syncthreads();
-        double L[NV], divu;
+        T L[NV], divu;
         {
             const int f = ty * (TX + 1) + tx;
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * g.inv_dx[0];
-            divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * g.inv_dx[0];
+            for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * idx;
+            divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * idx;
         }
 
         if constexpr (NDIM >= 2) {
@@ -199,19 +199,19 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li], s_plane[v][r + 3][li],
-                               s_plane[v][r + 4][li], g.eps, s_pair[v][p], s_pair[NV + v][p]);
+                               s_plane[v][r + 4][li], eps, s_pair[v][p], s_pair[NV + v][p]);
             }
             __syncthreads();
             for (int f = tid; f < S::NFY; f += NT) {
                 const int c = f % TX, fr = f / TX;
                 const int pl = fr * TX + c;
-                double wL[NV], wR[NV], F[NV], uf;
+                T wL[NV], wR[NV], F[NV], uf;
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     wL[v] = s_pair[v][pl];
                     wR[v] = s_pair[NV + v][pl + TX];
                 }
-                const bool b = hllc<NDIM, (NDIM >= 2 ? 1 : 0)>(g, wL, wR, F, uf);
+                const bool b = hllc<NDIM, (NDIM >= 2 ? 1 : 0), T>(g, wL, wR, F, uf);
                 bad |= b && (x0 + c < g.n[0]) && (y0 + fr <= g.n[1]);
 #pragma unroll
                 for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
@@ -220,13 +220,13 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
             __syncthreads();
             const int f = ty * TX + tx;
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * g.inv_dx[1];
-            divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * g.inv_dx[1];
+            for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * idy;
+            divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
         }
         if constexpr (NDIM == 3) {
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] += (Fz[v] - Fzn[v]) * g.inv_dx[2];
-            divu += (Fzn[NV] - Fz[NV]) * g.inv_dx[2];
+            for (int v = 0; v < NV; v++) L[v] += (Fz[v] - Fzn[v]) * idz;
+            divu += (Fzn[NV] - Fz[NV]) * idz;
 #pragma unroll
             for (int v = 0; v <= NV; v++) Fz[v] = Fzn[v];
         }
@@ -250,30 +250,39 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
     if (bad) atomicOr(flag, 1);
 }
 
-template <int NDIM>
-int rhs_fused(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
-              const double *dt_dev, hipStream_t s)
+template <int NDIM, class T>
+int rhs_fused(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s)
 {
     using S = Shape<NDIM>;
     const Grid &g = h->g;
     dim3 grid((g.n[0] + S::TX - 1) / S::TX, NDIM >= 2 ? (g.n[1] + S::TY - 1) / S::TY : 1,
               NDIM == 3 ? (g.n[2] + kLZ - 1) / kLZ : 1);
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_fused<NDIM>), grid, dim3(S::NT), 0, s, g, q, q0, out, mode, dt, dt_dev, h->flag, kLZ);
+    hipLaunchKernelGGL((k_fused<NDIM, T>), grid, dim3(S::NT), 0, s, g, q, q0, out, mode, dt, dt_dev, h->flag, kLZ);
     timing_end(h, s);
     return hip_status(hipGetLastError(), "fused right-hand side launch");
 }
 
+template <class T>
+int rhs_fused_t(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt, const double *dt_dev,
+                hipStream_t s)
+{
+    const T *a = (const T *)q, *b = (const T *)q0;
+    T *o = (T *)out;
+    switch (h->g.ndim) {
+    case 1: return rhs_fused<1, T>(h, a, b, o, mode, dt, dt_dev, s);
+    case 2: return rhs_fused<2, T>(h, a, b, o, mode, dt, dt_dev, s);
+    default: return rhs_fused<3, T>(h, a, b, o, mode, dt, dt_dev, s);
+    }
+}
+
 }  // namespace
 
-int launch_rhs_fused(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+int launch_rhs_fused(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
                      const double *dt_dev, hipStream_t s)
 {
-    switch (h->g.ndim) {
-    case 1: return rhs_fused<1>(h, q, q0, out, mode, dt, dt_dev, s);
-    case 2: return rhs_fused<2>(h, q, q0, out, mode, dt, dt_dev, s);
-    default: return rhs_fused<3>(h, q, q0, out, mode, dt, dt_dev, s);
-    }
+    if (h->desc.precision == MFC_FP32_MIXED) return rhs_fused_t<float>(h, q, q0, out, mode, dt, dt_dev, s);
+    return rhs_fused_t<double>(h, q, q0, out, mode, dt, dt_dev, s);
 }
 
 }  // namespace mfc

@@ -53,12 +53,13 @@ void timing_end(mfc_grid *h, hipStream_t s, int slot = 0);
 
 // Launchers.  `q` has ghosts filled.  mode 0: out = rhs; mode s = 1, 2, 3:
 // out = a_s q0 + b_s (q + dt rhs) with the SSP-RK3 stage coefficients.
-// dt is *dt_dev if dt_dev is non-null, else dt.
-int launch_rhs_staged(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+// dt is *dt_dev if dt_dev is non-null, else dt.  Arrays hold double for
+// MFC_FP64 and float for MFC_FP32_MIXED.
+int launch_rhs_staged(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
                       const double *dt_dev, hipStream_t s);
-int launch_rhs_fused(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+int launch_rhs_fused(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
                      const double *dt_dev, hipStream_t s);
-int launch_rhs_split(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
                      const double *dt_dev, hipStream_t s);
 
 }  // namespace mfc

@@ -55,8 +55,8 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 
 // ------------------------------------------------------------ ghost fill
 // One thread per (variable, ghost layer, side, face-slab cell) of dimension d.
-__global__ void __launch_bounds__(kThreads) k_ghosts(Grid g, double *__restrict__ q, int nv, int d, int bc_lo,
-                                                     int bc_hi)
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_ghosts(Grid g, T *__restrict__ q, int nv, int d, int bc_lo, int bc_hi)
 {
     int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
     int n1 = g.n[o1], n2 = g.n[o2], n = g.n[d];
@@ -88,31 +88,31 @@ __global__ void __launch_bounds__(kThreads) k_ghosts(Grid g, double *__restrict_
 }
 
 // ------------------------------------------------------ EOS conversions
-template <int NDIM>
-__global__ void __launch_bounds__(kThreads) k_p2c(Grid g, const double *__restrict__ w, double *__restrict__ q)
+template <int NDIM, class T>
+__global__ void __launch_bounds__(kThreads) k_p2c(Grid g, const T *__restrict__ w, T *__restrict__ q)
 {
     constexpr int NV = 4 + NDIM;
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.vstride) return;
-    double wc[NV], qc[NV];
+    T wc[NV], qc[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) wc[v] = w[v * g.vstride + c];
-    prim_to_cons<NDIM>(g, wc, qc);
+    prim_to_cons<NDIM, T>(g, wc, qc);
 #pragma unroll
     for (int v = 0; v < NV; v++) q[v * g.vstride + c] = qc[v];
 }
 
-template <int NDIM>
-__global__ void __launch_bounds__(kThreads) k_c2p(Grid g, const double *__restrict__ q, double *__restrict__ w,
+template <int NDIM, class T>
+__global__ void __launch_bounds__(kThreads) k_c2p(Grid g, const T *__restrict__ q, T *__restrict__ w,
                                                   int *__restrict__ flag)
 {
     constexpr int NV = 4 + NDIM;
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.vstride) return;
-    double qc[NV], wc[NV];
+    T qc[NV], wc[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
-    if (cons_to_prim<NDIM>(g, qc, wc)) atomicOr(flag, 1);
+    if (cons_to_prim<NDIM, T>(g, qc, wc)) atomicOr(flag, 1);
 #pragma unroll
     for (int v = 0; v < NV; v++) w[v * g.vstride + c] = wc[v];
 }
@@ -121,8 +121,8 @@ __global__ void __launch_bounds__(kThreads) k_c2p(Grid g, const double *__restri
 // Per-block maxima of max_d (|u_d| + c) over interior cells (grid-stride),
 // reduced within each wavefront by butterfly shuffles and across the block
 // through LDS.  Maxima are exact and order-independent.
-template <int NDIM>
-__global__ void __launch_bounds__(kReduceThreads) k_wavespeed(Grid g, const double *__restrict__ q,
+template <int NDIM, class T>
+__global__ void __launch_bounds__(kReduceThreads) k_wavespeed(Grid g, const T *__restrict__ q,
                                                               double *__restrict__ partial, int *__restrict__ flag)
 {
     constexpr int NV = 4 + NDIM, E = 2 + NDIM, A = 3 + NDIM;
@@ -136,15 +136,15 @@ __global__ void __launch_bounds__(kReduceThreads) k_wavespeed(Grid g, const doub
         int j = (int)(r % g.n[1]);
         int k = (int)(r / g.n[1]);
         int64_t c = (int64_t)(k + g.off[2]) * g.stride[2] + (int64_t)(j + g.off[1]) * g.stride[1] + (i + g.off[0]);
-        double qc[NV], wc[NV];
+        T qc[NV], wc[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
-        bad |= cons_to_prim<NDIM>(g, qc, wc);
+        bad |= cons_to_prim<NDIM, T>(g, qc, wc);
         double Gam, Pi;
-        mixture(g, wc[A], Gam, Pi);
-        double cs = __builtin_sqrt(sound2(Gam, Pi, wc[0] + wc[1], wc[E]));
+        mixture<double>(g, double(wc[A]), Gam, Pi);
+        double cs = __builtin_sqrt(sound2<double>(Gam, Pi, double(wc[0]) + double(wc[1]), double(wc[E])));
 #pragma unroll
-        for (int d = 0; d < NDIM; d++) smax = __builtin_fmax(smax, __builtin_fabs(wc[2 + d]) + cs);
+        for (int d = 0; d < NDIM; d++) smax = __builtin_fmax(smax, __builtin_fabs(double(wc[2 + d])) + cs);
     }
     if (bad) atomicOr(flag, 2);
 #pragma unroll
@@ -220,7 +220,9 @@ int validate(const mfc_grid_desc *d)
     if (d->recon != MFC_RECON_WENO5 && d->recon != MFC_RECON_LEARNED) return fail(MFC_E_ARG, "unknown recon");
     if (d->kernel != MFC_KERNEL_FUSED && d->kernel != MFC_KERNEL_STAGED && d->kernel != MFC_KERNEL_SPLIT)
         return fail(MFC_E_ARG, "unknown kernel");
-    if (d->precision != MFC_FP64) return fail(MFC_E_UNSUPPORTED, "only MFC_FP64 is built in this version");
+    if (d->precision == MFC_FP32_MIXED && d->kernel == MFC_KERNEL_STAGED)
+        return fail(MFC_E_UNSUPPORTED, "the staged path is FP64 only");
+    if (d->kernel == MFC_KERNEL_SPLIT && d->ndim != 3) return fail(MFC_E_UNSUPPORTED, "the split path is 3D only");
     if (d->recon != MFC_RECON_WENO5) return fail(MFC_E_UNSUPPORTED, "only MFC_RECON_WENO5 is built in this version");
     return MFC_OK;
 }
@@ -245,7 +247,7 @@ int by_ndim(int ndim, F f)
     }
 }
 
-int rhs_dispatch(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+int rhs_dispatch(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
                  const double *dt_dev, hipStream_t s)
 {
     if (h->desc.kernel == MFC_KERNEL_STAGED) return launch_rhs_staged(h, q, q0, out, mode, dt, dt_dev, s);
@@ -253,29 +255,46 @@ int rhs_dispatch(mfc_grid *h, const double *q, const double *q0, double *out, in
     return launch_rhs_fused(h, q, q0, out, mode, dt, dt_dev, s);
 }
 
-int fill_ghosts(mfc_grid *h, double *q, hipStream_t s)
+bool is_fp32(const mfc_grid *h) { return h->desc.precision == MFC_FP32_MIXED; }
+
+template <class T>
+void fill_ghosts_t(mfc_grid *h, T *q, hipStream_t s)
 {
     const Grid &g = h->g;
     for (int d = 0; d < g.ndim; d++) {
         int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
         int64_t count = (int64_t)2 * NG * g.n[o1] * g.n[o2] * h->nvar;
-        hipLaunchKernelGGL(k_ghosts, dim3(blocks_for(count)), dim3(kThreads), 0, s, g, q, h->nvar, d,
+        hipLaunchKernelGGL((k_ghosts<T>), dim3(blocks_for(count)), dim3(kThreads), 0, s, g, q, h->nvar, d,
                            h->desc.bc[2 * d], h->desc.bc[2 * d + 1]);
     }
+}
+
+int fill_ghosts(mfc_grid *h, void *q, hipStream_t s)
+{
+    if (is_fp32(h)) fill_ghosts_t<float>(h, (float *)q, s);
+    else fill_ghosts_t<double>(h, (double *)q, s);
     return hip_status(hipGetLastError(), "ghost fill launch");
 }
 
-int wavespeed(mfc_grid *h, const double *q, hipStream_t s)
+template <class T>
+void wavespeed_t(mfc_grid *h, const T *q, hipStream_t s)
 {
     by_ndim(h->g.ndim, [&](auto nd) {
-        hipLaunchKernelGGL((k_wavespeed<decltype(nd)::value>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, h->g, q,
-                           h->partial, h->flag);
+        hipLaunchKernelGGL((k_wavespeed<decltype(nd)::value, T>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s,
+                           h->g, q, h->partial, h->flag);
         return 0;
     });
+}
+
+int wavespeed(mfc_grid *h, const void *q, hipStream_t s)
+{
+    if (is_fp32(h)) wavespeed_t<float>(h, (const float *)q, s);
+    else wavespeed_t<double>(h, (const double *)q, s);
     return hip_status(hipGetLastError(), "wave-speed launch");
 }
 
-int64_t state_bytes(const mfc_grid *h) { return (int64_t)h->nvar * h->cells_padded * 8; }
+int64_t elem_bytes(const mfc_grid *h) { return is_fp32(h) ? 4 : 8; }
+int64_t state_bytes(const mfc_grid *h) { return (int64_t)h->nvar * h->cells_padded * elem_bytes(h); }
 
 }  // namespace
 }  // namespace mfc
@@ -368,8 +387,8 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
         alloc((void **)&h->recm, sb);
         alloc((void **)&h->faces, (int64_t)3 * (h->nvar + 1) * h->cells_padded * 8);
     }
-    if (desc->kernel == MFC_KERNEL_SPLIT && desc->ndim == 3)
-        alloc((void **)&h->lxy, (int64_t)(h->nvar + 1) * h->cells_padded * 8);
+    if (desc->kernel == MFC_KERNEL_SPLIT)
+        alloc((void **)&h->lxy, (int64_t)(h->nvar + 1) * h->cells_padded * elem_bytes(h));
     alloc((void **)&h->partial, kReduceBlocks * 8);
     alloc((void **)&h->scalars, 4 * 8);
     alloc((void **)&h->flag, 8);
@@ -393,7 +412,7 @@ int mfc_state_layout(const mfc_grid *h, int64_t *nvar, int64_t padded[3], int64_
     if (nvar) *nvar = h->nvar;
     if (padded)
         for (int d = 0; d < 3; d++) padded[d] = h->g.p[d];
-    if (elem_bytes) *elem_bytes = h->desc.precision == MFC_FP64 ? 8 : 4;
+    if (elem_bytes) *elem_bytes = mfc::elem_bytes(h);
     return MFC_OK;
 }
 
@@ -405,8 +424,13 @@ int mfc_prim_to_cons(mfc_grid *h, const void *w, void *q, void *stream)
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     by_ndim(h->g.ndim, [&](auto nd) {
-        hipLaunchKernelGGL((k_p2c<decltype(nd)::value>), dim3(blocks_for(h->cells_padded)), dim3(kThreads), 0, s,
-                           h->g, (const double *)w, (double *)q);
+        constexpr int ND = decltype(nd)::value;
+        if (is_fp32(h))
+            hipLaunchKernelGGL((k_p2c<ND, float>), dim3(blocks_for(h->cells_padded)), dim3(kThreads), 0, s, h->g,
+                               (const float *)w, (float *)q);
+        else
+            hipLaunchKernelGGL((k_p2c<ND, double>), dim3(blocks_for(h->cells_padded)), dim3(kThreads), 0, s, h->g,
+                               (const double *)w, (double *)q);
         return 0;
     });
     return hip_status(hipGetLastError(), "prim_to_cons launch");
@@ -420,8 +444,13 @@ int mfc_cons_to_prim(mfc_grid *h, const void *q, void *w, void *stream)
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     by_ndim(h->g.ndim, [&](auto nd) {
-        hipLaunchKernelGGL((k_c2p<decltype(nd)::value>), dim3(blocks_for(h->cells_padded)), dim3(kThreads), 0, s,
-                           h->g, (const double *)q, (double *)w, h->flag);
+        constexpr int ND = decltype(nd)::value;
+        if (is_fp32(h))
+            hipLaunchKernelGGL((k_c2p<ND, float>), dim3(blocks_for(h->cells_padded)), dim3(kThreads), 0, s, h->g,
+                               (const float *)q, (float *)w, h->flag);
+        else
+            hipLaunchKernelGGL((k_c2p<ND, double>), dim3(blocks_for(h->cells_padded)), dim3(kThreads), 0, s, h->g,
+                               (const double *)q, (double *)w, h->flag);
         return 0;
     });
     return hip_status(hipGetLastError(), "cons_to_prim launch");
@@ -432,7 +461,7 @@ int mfc_fill_ghosts(mfc_grid *h, void *q, void *stream)
     if (bad_handle(h) || !q) return fail(MFC_E_ARG, "null argument");
     int st = set_device(h);
     if (st) return st;
-    return fill_ghosts(h, (double *)q, (hipStream_t)stream);
+    return fill_ghosts(h, q, (hipStream_t)stream);
 }
 
 int mfc_rhs(mfc_grid *h, const void *q, void *rhs, void *stream)
@@ -441,7 +470,7 @@ int mfc_rhs(mfc_grid *h, const void *q, void *rhs, void *stream)
     if (q == rhs) return fail(MFC_E_ARG, "q and rhs must be distinct");
     int st = set_device(h);
     if (st) return st;
-    return rhs_dispatch(h, (const double *)q, nullptr, (double *)rhs, 0, 0.0, nullptr, (hipStream_t)stream);
+    return rhs_dispatch(h, q, nullptr, rhs, 0, 0.0, nullptr, (hipStream_t)stream);
 }
 
 int mfc_max_wavespeed(mfc_grid *h, const void *q, double *smax_host, void *stream)
@@ -450,7 +479,7 @@ int mfc_max_wavespeed(mfc_grid *h, const void *q, double *smax_host, void *strea
     int st = set_device(h);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
-    st = wavespeed(h, (const double *)q, s);
+    st = wavespeed(h, q, s);
     if (st) return st;
     double *partial = (double *)std::malloc(kReduceBlocks * sizeof(double));
     int flag = 0;
@@ -480,7 +509,7 @@ int mfc_rk3_step(mfc_grid *h, void *qv, double cfl, double dt, void *stream)
     int st = set_device(h);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
-    double *q = (double *)qv, *A = (double *)h->stage_a, *B = (double *)h->stage_b;
+    void *q = qv, *A = h->stage_a, *B = h->stage_b;
     const double *dt_dev = h->scalars + 1;
     if ((st = fill_ghosts(h, q, s))) return st;
     if (cfl > 0.0) {

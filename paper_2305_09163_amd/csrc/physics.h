@@ -4,10 +4,19 @@
 // Everything here is inlined into the kernels; the state ordering is
 // [a1r1, a2r2, mom_1..mom_NDIM, rhoE, alpha1] (conservative) and
 // [a1r1, a2r2, u_1..u_NDIM, p, alpha1] (primitive).
+//
+// Two precisions share the code, selected by the storage type T:
+//   double  everything in FP64;
+//   float   FP32 storage, reconstruction and Riemann solve, except the
+//           mixture pressure recovery p = (rho E - rho|u|^2/2 - Pi)/Gamma and
+//           the HLLC contact speed s*, which are evaluated in FP64 because
+//           both cancel large terms (Pi ~ 8e8 Pa in water against p ~ 1e5).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace mfc {
 
@@ -29,10 +38,10 @@ struct Grid {
 };
 
 // ---------------------------------------------------------------- reciprocal
-// Correctly-rounded-in-practice double reciprocal: hardware estimate refined
-// by two Newton-Raphson steps (r <- r + r (1 - x r)), each doubling the
-// number of correct bits.  Used where a full IEEE division sequence would be
-// the dominant cost; inputs are normal, finite and nonzero on physical states.
+// Double reciprocal: hardware estimate refined by two Newton-Raphson steps
+// (r <- r + r (1 - x r)), each doubling the number of correct bits.  Used
+// where a full IEEE division sequence would be the dominant cost; inputs are
+// normal, finite and nonzero on physical states.
 __device__ __forceinline__ double rcp(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
@@ -42,68 +51,86 @@ __device__ __forceinline__ double rcp(double x)
     r = __builtin_fma(r, e, r);
     return r;
 }
+// Single reciprocal: the hardware instruction (1 ulp).
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double sqrtT(double a) { return __builtin_sqrt(a); }
+__device__ __forceinline__ float sqrtT(float a) { return __builtin_sqrtf(a); }
+__device__ __forceinline__ double fminT(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float fminT(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double fmaxT(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float fmaxT(float a, float b) { return __builtin_fmaxf(a, b); }
 
 // ------------------------------------------------------------------- EOS
-__device__ __forceinline__ void mixture(const Grid &g, double a1, double &Gam, double &Pi)
+template <class T>
+__device__ __forceinline__ void mixture(const Grid &g, T a1, T &Gam, T &Pi)
 {
-    double a2 = 1.0 - a1;
-    Gam = a1 * g.g1 + a2 * g.g2;
-    Pi = a1 * g.h1 + a2 * g.h2;
+    T a2 = T(1) - a1;
+    Gam = a1 * T(g.g1) + a2 * T(g.g2);
+    Pi = a1 * T(g.h1) + a2 * T(g.h2);
 }
 
 // Frozen mixture sound speed squared, c^2 = ((Gamma + 1) p + Pi) / (Gamma rho).
-__device__ __forceinline__ double sound2(double Gam, double Pi, double rho, double p)
+template <class T>
+__device__ __forceinline__ T sound2(T Gam, T Pi, T rho, T p)
 {
-    return __builtin_fma(Gam + 1.0, p, Pi) * rcp(Gam * rho);
+    return fmaT(Gam + T(1), p, Pi) * rcp(Gam * rho);
 }
 
-__device__ __forceinline__ bool nonphysical(double rho, double c2)
+template <class T>
+__device__ __forceinline__ bool nonphysical(T rho, T c2)
 {
-    return !(rho > 0.0) || !(c2 > 0.0) || !__builtin_isfinite(rho) || !__builtin_isfinite(c2);
+    return !(rho > T(0)) || !(c2 > T(0)) || !__builtin_isfinite(rho) || !__builtin_isfinite(c2);
 }
 
-// Conservative -> primitive for one cell; returns true if non-physical.
-template <int NDIM>
-__device__ __forceinline__ bool cons_to_prim(const Grid &g, const double *q, double *w)
+// Conservative -> primitive for one cell; returns true if non-physical
+// (rho <= 0, c^2 <= 0 or non-finite).  For float storage the pressure is
+// recovered in FP64 from the stored (float) energy, momenta and fractions.
+template <int NDIM, class T>
+__device__ __forceinline__ bool cons_to_prim(const Grid &g, const T *q, T *w)
 {
     constexpr int E = 2 + NDIM, A = 3 + NDIM;
-    double rho = q[0] + q[1];
-    double ir = rcp(rho);
-    double Gam, Pi;
-    mixture(g, q[A], Gam, Pi);
-    double ke = 0.0;
+    const T rho = q[0] + q[1];
+    const T ir = rcp(rho);
     w[0] = q[0];
     w[1] = q[1];
 #pragma unroll
-    for (int m = 0; m < NDIM; m++) {
-        w[2 + m] = q[2 + m] * ir;
-        ke += q[2 + m] * w[2 + m];
-    }
-    const double iG = rcp(Gam);
-    w[E] = (q[E] - 0.5 * ke - Pi) * iG;
+    for (int m = 0; m < NDIM; m++) w[2 + m] = q[2 + m] * ir;
     w[A] = q[A];
+    double ke = 0.0;
+#pragma unroll
+    for (int m = 0; m < NDIM; m++) ke += double(q[2 + m]) * double(w[2 + m]);
+    double Gam, Pi;
+    mixture<double>(g, double(q[A]), Gam, Pi);
+    const double iG = rcp(Gam);
+    const double p = (double(q[E]) - 0.5 * ke - Pi) * iG;
+    w[E] = T(p);
     // c^2 = ((Gamma + 1) p + Pi) / (Gamma rho): its sign and finiteness
     // without the division
-    const double num = __builtin_fma(Gam + 1.0, w[E], Pi);
-    return !(rho > 0.0) || !(num * iG > 0.0) || !__builtin_isfinite(rho) || !__builtin_isfinite(num * iG * ir);
+    const double num = __builtin_fma(Gam + 1.0, p, Pi);
+    const double dr = double(rho), di = double(ir);
+    return !(dr > 0.0) || !(num * iG > 0.0) || !__builtin_isfinite(dr) || !__builtin_isfinite(num * iG * di);
 }
 
-template <int NDIM>
-__device__ __forceinline__ void prim_to_cons(const Grid &g, const double *w, double *q)
+// Primitive -> conservative for one cell (energy assembled in FP64).
+template <int NDIM, class T>
+__device__ __forceinline__ void prim_to_cons(const Grid &g, const T *w, T *q)
 {
     constexpr int E = 2 + NDIM, A = 3 + NDIM;
-    double rho = w[0] + w[1];
+    const double rho = double(w[0]) + double(w[1]);
     double Gam, Pi;
-    mixture(g, w[A], Gam, Pi);
+    mixture<double>(g, double(w[A]), Gam, Pi);
     double u2 = 0.0;
     q[0] = w[0];
     q[1] = w[1];
 #pragma unroll
     for (int m = 0; m < NDIM; m++) {
-        q[2 + m] = rho * w[2 + m];
-        u2 += w[2 + m] * w[2 + m];
+        q[2 + m] = T(rho * double(w[2 + m]));
+        u2 += double(w[2 + m]) * double(w[2 + m]);
     }
-    q[E] = Gam * w[E] + Pi + 0.5 * rho * u2;
+    q[E] = T(Gam * double(w[E]) + Pi + 0.5 * rho * u2);
     q[A] = w[A];
 }
 
@@ -119,12 +146,16 @@ __device__ __forceinline__ void prim_to_cons(const Grid &g, const double *w, dou
 //     (3 beta_0 = a (10a - 11b) + 4b^2, 3 beta_1 = c (4c - 5a) + 4a^2,
 //     3 beta_2 = c (10c - 11d) + 4d^2); the weights depend only on ratios of
 //     (eps + beta_r)^2, so the common factor cancels;
-//   - a_r = d_r/(eps + beta_r)^2 is normalised through common denominators,
-//     a_r ~ d_r prod_{s != r} (eps + beta_s)^2, with the ideal weights scaled
-//     by 10 (1, 6, 3 and 3, 6, 1), so one reciprocal serves both faces;
 //   - the candidates enter as increments over v0 scaled by 6
 //     (6 (p_r - v0) at x_{i+1/2}: 5a - 2b, 2c + a, 4c - d; at x_{i-1/2}:
 //     b - 4a, -(2a + c), 2d - 5c), which reproduces constants exactly.
+//   - FP64: a_r = d_r/(eps + beta_r)^2 is normalised through common
+//     denominators, a_r ~ d_r prod_{s != r} (eps + beta_s)^2, so one
+//     reciprocal serves both faces;
+//   - FP32: (eps + beta)^2 can exceed the float range across strong jumps,
+//     so the weights use the ratio form a_r ~ d_r ((eps + beta_min)/(eps + beta_r))^2,
+//     every term of which lies in [0, d_r].
+// Ideal weights are scaled by 10: (1, 6, 3) at x_{i+1/2}, (3, 6, 1) at x_{i-1/2}.
 __device__ __forceinline__ void weno5_pair(double vm2, double vm1, double v0, double vp1, double vp2,
                                            double eps, double &plus, double &minus)
 {
@@ -146,6 +177,42 @@ __device__ __forceinline__ void weno5_pair(double vm2, double vm1, double v0, do
     minus = __builtin_fma(nm, sp * r, v0);
 }
 
+__device__ __forceinline__ void weno5_pair(float vm2, float vm1, float v0, float vp1, float vp2, float eps,
+                                           float &plus, float &minus)
+{
+    const float b = vm1 - vm2, a = v0 - vm1, c = vp1 - v0, d = vp2 - vp1;
+    const float e3 = 3.0f * eps;
+    const float e0 = __builtin_fmaf(a, __builtin_fmaf(10.0f, a, -11.0f * b), __builtin_fmaf(4.0f * b, b, e3));
+    const float e1 = __builtin_fmaf(c, __builtin_fmaf(4.0f, c, -5.0f * a), __builtin_fmaf(4.0f * a, a, e3));
+    const float e2 = __builtin_fmaf(c, __builtin_fmaf(10.0f, c, -11.0f * d), __builtin_fmaf(4.0f * d, d, e3));
+    const float emin = __builtin_fminf(e0, __builtin_fminf(e1, e2));
+    const float t0 = emin * rcp(e0), t1 = emin * rcp(e1), t2 = emin * rcp(e2);
+    const float m0 = t0 * t0, m1 = 6.0f * (t1 * t1), m2 = t2 * t2;
+    const float sp = __builtin_fmaf(3.0f, m2, m0 + m1);
+    const float sm = __builtin_fmaf(3.0f, m0, m1 + m2);
+    const float np = __builtin_fmaf(3.0f * m2, __builtin_fmaf(4.0f, c, -d),
+                                   __builtin_fmaf(m1, __builtin_fmaf(2.0f, c, a), m0 * __builtin_fmaf(5.0f, a, -2.0f * b)));
+    const float nm = __builtin_fmaf(m2, __builtin_fmaf(2.0f, d, -5.0f * c),
+                                   __builtin_fmaf(m1, -__builtin_fmaf(2.0f, a, c), 3.0f * m0 * __builtin_fmaf(-4.0f, a, b)));
+    const float r = rcp(6.0f * (sp * sm));
+    plus = __builtin_fmaf(np, sm * r, v0);
+    minus = __builtin_fmaf(nm, sp * r, v0);
+}
+
+// The contact speed s* of the HLLC solver from the two sides' values.
+// FP64 for both storage types: numerator and denominator cancel at material
+// interfaces (equal pressures, opposite wave speeds).
+template <class T>
+__device__ __forceinline__ T contact_speed(T pL, T pR, T mL, T mR, T uL, T uR)
+{
+    if constexpr (std::is_same<T, double>::value) {
+        return (pR - pL + mL * uL - mR * uR) * rcp(mL - mR);
+    } else {
+        const double num = double(pR) - double(pL) + double(mL) * double(uL) - double(mR) * double(uR);
+        return T(num * rcp(double(mL) - double(mR)));
+    }
+}
+
 // ------------------------------------------------------------------- HLLC
 // HLLC flux through a face normal to DIR between primitive states wL and wR
 // (NV = 4 + NDIM values each).  F[0 .. NV-2]: flux of the conserved rows;
@@ -155,60 +222,59 @@ __device__ __forceinline__ void weno5_pair(double vm2, double vm1, double v0, do
 // exactly as in the case table: s_L >= 0 -> L, s_R <= 0 -> R, otherwise L*
 // if s* >= 0 and R* if not; alpha1 jumps only across the contact.
 // Returns true if either side is non-physical.
-template <int NDIM, int DIR>
-__device__ __forceinline__ bool hllc(const Grid &g, const double *wL, const double *wR, double *F, double &uf)
+template <int NDIM, int DIR, class T>
+__device__ __forceinline__ bool hllc(const Grid &g, const T *wL, const T *wR, T *F, T &uf)
 {
     constexpr int NV = 4 + NDIM, E = 2 + NDIM, A = 3 + NDIM;
-    const double rhoL = wL[0] + wL[1], rhoR = wR[0] + wR[1];
-    const double uL = wL[2 + DIR], uR = wR[2 + DIR];
-    const double pL = wL[E], pR = wR[E];
-    double GL, PL, GR, PR;
-    mixture(g, wL[A], GL, PL);
-    mixture(g, wR[A], GR, PR);
-    const double c2L = sound2(GL, PL, rhoL, pL), c2R = sound2(GR, PR, rhoR, pR);
-    const bool bad = nonphysical(rhoL, c2L) || nonphysical(rhoR, c2R);
-    const double cL = __builtin_sqrt(c2L), cR = __builtin_sqrt(c2R);
-    const double sL = __builtin_fmin(uL - cL, uR - cR);
-    const double sR = __builtin_fmax(uL + cL, uR + cR);
-    const double mL = rhoL * (sL - uL), mR = rhoR * (sR - uR);
-    const double sS = (pR - pL + mL * uL - mR * uR) * rcp(mL - mR);
+    const T rhoL = wL[0] + wL[1], rhoR = wR[0] + wR[1];
+    const T uL = wL[2 + DIR], uR = wR[2 + DIR];
+    const T pL = wL[E], pR = wR[E];
+    T GL, PL, GR, PR;
+    mixture<T>(g, wL[A], GL, PL);
+    mixture<T>(g, wR[A], GR, PR);
+    const T c2L = sound2<T>(GL, PL, rhoL, pL), c2R = sound2<T>(GR, PR, rhoR, pR);
+    const bool bad = nonphysical<T>(rhoL, c2L) || nonphysical<T>(rhoR, c2R);
+    const T cL = sqrtT(c2L), cR = sqrtT(c2R);
+    const T sL = fminT(uL - cL, uR - cR);
+    const T sR = fmaxT(uL + cL, uR + cR);
+    const T mL = rhoL * (sL - uL), mR = rhoR * (sR - uR);
+    const T sS = contact_speed<T>(pL, pR, mL, mR, uL, uR);
 
-    const bool super_L = sL >= 0.0, super_R = sR <= 0.0;
-    const bool useL = super_L || (!super_R && sS >= 0.0);
+    const bool super_L = sL >= T(0), super_R = sR <= T(0);
+    const bool useL = super_L || (!super_R && sS >= T(0));
     const bool star = !super_L && !super_R;
 
     // the side whose state (plain or starred) is the fan at x/t = 0
-    double w[NV];
+    T w[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) w[v] = useL ? wL[v] : wR[v];
-    const double rho = useL ? rhoL : rhoR;
-    const double Gam = useL ? GL : GR, Pi = useL ? PL : PR;
-    const double sK = useL ? sL : sR;
-    const double un = w[2 + DIR], p = w[E];
-    double u2 = 0.0;
+    const T rho = useL ? rhoL : rhoR;
+    const T Gam = useL ? GL : GR, Pi = useL ? PL : PR;
+    const T sK = useL ? sL : sR;
+    const T un = w[2 + DIR], p = w[E];
+    T u2 = T(0);
 #pragma unroll
     for (int m = 0; m < NDIM; m++) u2 += w[2 + m] * w[2 + m];
-    const double En = Gam * p + Pi + 0.5 * rho * u2;
+    const T En = Gam * p + Pi + T(0.5) * rho * u2;
 
     // physical flux of that side
     F[0] = w[0] * un;
     F[1] = w[1] * un;
 #pragma unroll
-    for (int m = 0; m < NDIM; m++) F[2 + m] = rho * w[2 + m] * un + (m == DIR ? p : 0.0);
+    for (int m = 0; m < NDIM; m++) F[2 + m] = rho * w[2 + m] * un + (m == DIR ? p : T(0));
     F[E] = (En + p) * un;
 
     // star correction s_K (q*_K - q_K), with xi - 1 = (s* - u)/(s_K - s*)
-    const double sku = sK - un;
-    const double ism = rcp(sK - sS);
-    const double xim1 = (sS - un) * ism;
-    const double xi = sku * ism;
-    double dq[NV - 1];
+    const T ism = rcp(sK - sS);
+    const T xim1 = (sS - un) * ism;
+    const T xi = (sK - un) * ism;
+    T dq[NV - 1];
     dq[0] = xim1 * w[0];
     dq[1] = xim1 * w[1];
 #pragma unroll
     for (int m = 0; m < NDIM; m++) dq[2 + m] = (m == DIR) ? rho * (xi * sS - un) : xim1 * rho * w[2 + m];
     // xi (s* - u)(rho s* + p/(s_K - u)) = (s* - u)(xi rho s* + p/(s_K - s*))
-    dq[E] = xim1 * En + (sS - un) * __builtin_fma(xi * rho, sS, p * ism);
+    dq[E] = xim1 * En + (sS - un) * fmaT(xi * rho, sS, p * ism);
 #pragma unroll
     for (int v = 0; v < NV - 1; v++) F[v] = star ? F[v] + sK * dq[v] : F[v];
 

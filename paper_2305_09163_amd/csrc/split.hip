@@ -15,7 +15,9 @@
 //         source and the SSP-RK3 combination and writes the stage result.
 //
 // Neither kernel carries the other's state, so each fits its registers
-// without spilling; the price is one 64-byte round trip per cell through HBM.
+// without spilling; the price is one round trip of 8 values per cell through
+// HBM.  Both kernels are instantiated for FP64 and for the FP32 storage form
+// (T = float; the x+y part is kept in the same type).
 #include "internal.h"
 
 namespace mfc {
@@ -40,25 +42,28 @@ __device__ __forceinline__ int64_t offset(const Grid &g, int i, int j, int k)
 // Load and convert one cell; flag only cells the method reads (at most one
 // coordinate outside the interior: out-of-grid lanes of ragged tiles may
 // touch never-written edge ghosts whose results are discarded).
-__device__ __forceinline__ bool load_prim3(const Grid &g, const double *__restrict__ q, int i, int j, int k, double *w)
+template <class T>
+__device__ __forceinline__ bool load_prim3(const Grid &g, const T *__restrict__ q, int i, int j, int k, T *w)
 {
     constexpr int NV = 7;
     const int64_t c = offset(g, i, j, k);
-    double qc[NV];
+    T qc[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
-    const bool bad = cons_to_prim<3>(g, qc, w);
+    const bool bad = cons_to_prim<3, T>(g, qc, w);
     const int outside = (i < 0 || i >= g.n[0]) + (j < 0 || j >= g.n[1]) + (k < 0 || k >= g.n[2]);
     return bad && outside <= 1;
 }
 
+template <class T>
 __global__ void __launch_bounds__(NT, 2)
-    k_xy(Grid g, const double *__restrict__ q, double *__restrict__ lxy, int *__restrict__ flag)
+    k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag)
 {
     constexpr int NV = 7;
-    __shared__ double s_plane[NV][PY][PX];
-    __shared__ double s_pair[2 * NV][NP];
-    __shared__ double s_flux[NV + 1][NF];
+    __shared__ T s_plane[NV][PY][PX];
+    __shared__ T s_pair[2 * NV][NP];
+    __shared__ T s_flux[NV + 1][NF];
+    const T eps = T(g.eps);
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -72,8 +77,8 @@ __global__ void __launch_bounds__(NT, 2)
     for (int k = z0; k < z1; k++) {
         // ---- plane k (own cell + x/y halos) into LDS as primitives
         {
-            double w[NV];
-            bad |= load_prim3(g, q, min(gx, xmax), min(gy, ymax), k, w);
+            T w[NV];
+            bad |= load_prim3<T>(g, q, min(gx, xmax), min(gy, ymax), k, w);
 #pragma unroll
             for (int v = 0; v < NV; v++) s_plane[v][ty + NG][tx + NG] = w[v];
         }
@@ -89,8 +94,8 @@ __global__ void __launch_bounds__(NT, 2)
                 li = c + NG;
                 lj = r < NG ? r : TY + r;
             }
-            double w[NV];
-            bad |= load_prim3(g, q, min(x0 + li - NG, xmax), min(y0 + lj - NG, ymax), k, w);
+            T w[NV];
+            bad |= load_prim3<T>(g, q, min(x0 + li - NG, xmax), min(y0 + lj - NG, ymax), k, w);
 #pragma unroll
             for (int v = 0; v < NV; v++) s_plane[v][lj][li] = w[v];
         }
@@ -101,33 +106,34 @@ __global__ void __launch_bounds__(NT, 2)
             const int row = p / (TX + 2), c = p % (TX + 2);
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                const double *s = &s_plane[v][row + NG][c];
-                weno5_pair(s[0], s[1], s[2], s[3], s[4], g.eps, s_pair[v][p], s_pair[NV + v][p]);
+                const T *s = &s_plane[v][row + NG][c];
+                weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
             }
         }
         __syncthreads();
         for (int f = tid; f < NFX; f += NT) {
             const int row = f / (TX + 1), fi = f % (TX + 1);
             const int pl = row * (TX + 2) + fi;
-            double wL[NV], wR[NV], F[NV], uf;
+            T wL[NV], wR[NV], F[NV], uf;
 #pragma unroll
             for (int v = 0; v < NV; v++) {
                 wL[v] = s_pair[v][pl];
                 wR[v] = s_pair[NV + v][pl + 1];
             }
-            const bool b = hllc<3, 0>(g, wL, wR, F, uf);
+            const bool b = hllc<3, 0, T>(g, wL, wR, F, uf);
             bad |= b && (y0 + row < g.n[1]) && (x0 + fi <= g.n[0]);
 #pragma unroll
             for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
             s_flux[NV][f] = uf;
         }
         __syncthreads();
-        double L[NV], divu;
+        const T idx = T(g.inv_dx[0]), idy = T(g.inv_dx[1]);
+        T L[NV], divu;
         {
             const int f = ty * (TX + 1) + tx;
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * g.inv_dx[0];
-            divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * g.inv_dx[0];
+            for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * idx;
+            divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * idx;
         }
         // ---- y: reconstruct rows -1 .. TY of every column, then the faces
         for (int p = tid; p < NPY; p += NT) {
@@ -136,19 +142,19 @@ __global__ void __launch_bounds__(NT, 2)
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li], s_plane[v][r + 3][li],
-                           s_plane[v][r + 4][li], g.eps, s_pair[v][p], s_pair[NV + v][p]);
+                           s_plane[v][r + 4][li], eps, s_pair[v][p], s_pair[NV + v][p]);
         }
         __syncthreads();
         for (int f = tid; f < NFY; f += NT) {
             const int c = f % TX, fr = f / TX;
             const int pl = fr * TX + c;
-            double wL[NV], wR[NV], F[NV], uf;
+            T wL[NV], wR[NV], F[NV], uf;
 #pragma unroll
             for (int v = 0; v < NV; v++) {
                 wL[v] = s_pair[v][pl];
                 wR[v] = s_pair[NV + v][pl + TX];
             }
-            const bool b = hllc<3, 1>(g, wL, wR, F, uf);
+            const bool b = hllc<3, 1, T>(g, wL, wR, F, uf);
             bad |= b && (x0 + c < g.n[0]) && (y0 + fr <= g.n[1]);
 #pragma unroll
             for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
@@ -158,8 +164,8 @@ __global__ void __launch_bounds__(NT, 2)
         {
             const int f = ty * TX + tx;
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * g.inv_dx[1];
-            divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * g.inv_dx[1];
+            for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * idy;
+            divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
         }
         if (own) {
             const int64_t c = offset(g, gx, gy, k);
@@ -177,45 +183,47 @@ __global__ void __launch_bounds__(NT, 2)
 // columns (64 consecutive x per wavefront: coalesced plane loads) and march
 // through kLZ planes, starting two planes early to reconstruct cell z0-1 and
 // solve face z0-1/2 without writing.
+template <class T>
 __global__ void __launch_bounds__(kZX * kZY, 2)
-    k_z(Grid g, const double *__restrict__ q, const double *q0, double *out, const double *__restrict__ lxy,
-        int mode, double dt, const double *__restrict__ dt_dev, int *__restrict__ flag)
+    k_z(Grid g, const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ lxy, int mode, double dt,
+        const double *__restrict__ dt_dev, int *__restrict__ flag)
 {
     constexpr int NV = 7, A = 6;
+    const T eps = T(g.eps), idz = T(g.inv_dx[2]);
     const int gx = blockIdx.x * kZX + threadIdx.x % kZX;
     const int gy = blockIdx.y * kZY + threadIdx.x / kZX;
     if (gx >= g.n[0] || gy >= g.n[1]) return;   // no barriers in this kernel
     const int z0 = blockIdx.z * kLZ, z1 = min(z0 + kLZ, g.n[2]);
-    const double hdt = mode ? (dt_dev ? *dt_dev : dt) : 0.0;
-    const double ca = mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0);
-    const double cb = mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0);
+    const T hdt = T(mode ? (dt_dev ? *dt_dev : dt) : 0.0);
+    const T ca = T(mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0));
+    const T cb = T(mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0));
     bool bad = false;
 
-    double zw[5][NV];   // primitives of planes k-1 .. k+3 after the shift
-    double pk[NV];      // cell k reconstructed at its + face
-    double Fz[NV + 1];  // flux and face velocity at k-1/2
+    T zw[5][NV];   // primitives of planes k-1 .. k+3 after the shift
+    T pk[NV];      // cell k reconstructed at its + face
+    T Fz[NV + 1];  // flux and face velocity at k-1/2
 #pragma unroll
-    for (int p = 1; p < 5; p++) bad |= load_prim3(g, q, gx, gy, z0 - 4 + p, zw[p]);
+    for (int p = 1; p < 5; p++) bad |= load_prim3<T>(g, q, gx, gy, z0 - 4 + p, zw[p]);
 
     for (int k = z0 - 2; k < z1; k++) {
 #pragma unroll
         for (int p = 0; p < 4; p++)
 #pragma unroll
             for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
-        bad |= load_prim3(g, q, gx, gy, k + 3, zw[4]);
-        double pn[NV], mn[NV], Fzn[NV + 1];
+        bad |= load_prim3<T>(g, q, gx, gy, k + 3, zw[4]);
+        T pn[NV], mn[NV], Fzn[NV + 1];
 #pragma unroll
         for (int v = 0; v < NV; v++)
-            weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], g.eps, pn[v], mn[v]);
-        if (k >= z0 - 1) bad |= hllc<3, 2>(g, pk, mn, Fzn, Fzn[NV]);
+            weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, pn[v], mn[v]);
+        if (k >= z0 - 1) bad |= hllc<3, 2, T>(g, pk, mn, Fzn, Fzn[NV]);
 #pragma unroll
         for (int v = 0; v < NV; v++) pk[v] = pn[v];
         if (k >= z0) {
             const int64_t c = offset(g, gx, gy, k);
-            double L[NV];
+            T L[NV];
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] = lxy[v * g.vstride + c] + (Fz[v] - Fzn[v]) * g.inv_dx[2];
-            const double divu = lxy[NV * g.vstride + c] + (Fzn[NV] - Fz[NV]) * g.inv_dx[2];
+            for (int v = 0; v < NV; v++) L[v] = lxy[v * g.vstride + c] + (Fz[v] - Fzn[v]) * idz;
+            const T divu = lxy[NV * g.vstride + c] + (Fzn[NV] - Fz[NV]) * idz;
             L[A] += zw[1][A] * divu;
             if (mode == 0) {
 #pragma unroll
@@ -234,22 +242,31 @@ __global__ void __launch_bounds__(kZX * kZY, 2)
     if (bad) atomicOr(flag, 1);
 }
 
-}  // namespace
-
-int launch_rhs_split(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
-                     const double *dt_dev, hipStream_t s)
+template <class T>
+int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s)
 {
     const Grid &g = h->g;
-    if (g.ndim != 3) return launch_rhs_fused(h, q, q0, out, mode, dt, dt_dev, s);
     dim3 gxy((g.n[0] + TX - 1) / TX, (g.n[1] + TY - 1) / TY, (g.n[2] + kPlanesXY - 1) / kPlanesXY);
     dim3 gz((g.n[0] + kZX - 1) / kZX, (g.n[1] + kZY - 1) / kZY, (g.n[2] + kLZ - 1) / kLZ);
+    T *lxy = (T *)h->lxy;
     timing_begin(h, s);
-    hipLaunchKernelGGL(k_xy, gxy, dim3(NT), 0, s, g, q, h->lxy, h->flag);
+    hipLaunchKernelGGL((k_xy<T>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag);
     timing_end(h, s);
     timing_begin(h, s, 1);
-    hipLaunchKernelGGL(k_z, gz, dim3(kZX * kZY), 0, s, g, q, q0, out, h->lxy, mode, dt, dt_dev, h->flag);
+    hipLaunchKernelGGL((k_z<T>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag);
     timing_end(h, s, 1);
     return hip_status(hipGetLastError(), "split right-hand side launch");
+}
+
+}  // namespace
+
+int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
+                     const double *dt_dev, hipStream_t s)
+{
+    if (h->g.ndim != 3) return fail(MFC_E_UNSUPPORTED, "the split path is 3D only");
+    if (h->desc.precision == MFC_FP32_MIXED)
+        return rhs_split<float>(h, (const float *)q, (const float *)q0, (float *)out, mode, dt, dt_dev, s);
+    return rhs_split<double>(h, (const double *)q, (const double *)q0, (double *)out, mode, dt, dt_dev, s);
 }
 
 }  // namespace mfc

@@ -179,9 +179,12 @@ int rhs_staged(mfc_grid *h, const double *q, const double *q0, double *out, int 
 
 }  // namespace
 
-int launch_rhs_staged(mfc_grid *h, const double *q, const double *q0, double *out, int mode, double dt,
+int launch_rhs_staged(mfc_grid *h, const void *qv, const void *q0v, void *outv, int mode, double dt,
                       const double *dt_dev, hipStream_t s)
 {
+    if (h->desc.precision != MFC_FP64) return fail(MFC_E_UNSUPPORTED, "the staged path is FP64 only");
+    const double *q = (const double *)qv, *q0 = (const double *)q0v;
+    double *out = (double *)outv;
     switch (h->g.ndim) {
     case 1: return rhs_staged<1>(h, q, q0, out, mode, dt, dt_dev, s);
     case 2: return rhs_staged<2>(h, q, q0, out, mode, dt, dt_dev, s);

@@ -53,9 +53,11 @@ def rel_linf(a, b, spec, floor_mom=0.0):
     return d / state_scales(spec, b, "max", floor_mom=floor_mom)
 
 
-def rel_l1(a, b, spec):
+def rel_l1(a, b, spec, floor_mom=0.0):
+    """floor_mom: per-cell momentum scale (see acoustic_floor); the momentum
+    denominator is at least cells * floor_mom."""
     d = np.abs(_interior(spec, a) - _interior(spec, b)).reshape(spec.nvar, -1).sum(axis=1)
-    return d / state_scales(spec, b, "sum")
+    return d / state_scales(spec, b, "sum", floor_mom=floor_mom * spec.cells)
 
 
 def rhs_err(ra, rb, q_ref, spec, cfl=0.3):
