@@ -154,6 +154,87 @@ int mfc_check(mfc_grid *g, void *stream);
 int mfc_set_kernel_timing(mfc_grid *g, int enable);
 int mfc_kernel_time(mfc_grid *g, int slot, double *ms_total, int64_t *launches);
 
+/* ------------------------------------------------------------------------
+ * Batched ensembles (project extension beside the method of Sec. 3).  Many
+ * independent 2D runs, each with its own grid size, fluids and boundaries,
+ * advanced together: every kernel of an SSP-RK3 step (Sec. 3.4) covers all
+ * runs, each run takes its own CFL step size (Sec. 1) on the device, and the
+ * right-hand side of every run is the one mfc_rhs defines.  A run advanced in
+ * a batch gives the same bits as the same run advanced alone with
+ * mfc_rk3_step (MFC_KERNEL_FUSED, same precision and cfl).
+ *
+ * State arrays stay owned by the caller: run r is a device array of the 2D
+ * state layout above (nvar 6, padded (n[0] + 6, n[1] + 6, 1)).  The batch
+ * owns two stage registers per run, the per-run step sizes and times, and
+ * the captured graph.  A batch must not be used from two host threads or
+ * two streams at once.
+ * ------------------------------------------------------------------------ */
+typedef struct mfc_batch mfc_batch;
+
+/* Launch configuration of the batched right-hand-side kernel:
+ *   shape  tile of one work item: 0 = 16 x 16, 1 = 32 x 8, 2 = 64 x 4 cells;
+ *   groups persistent workgroups per compute unit: 0 = 1, 1 = 2, 2 = 4;
+ *   xcd    1 = give each XCD a contiguous range of work items (neighbouring
+ *          tiles share one L2), 0 = deal items round-robin. */
+typedef struct {
+    int shape;
+    int groups;
+    int xcd;
+} mfc_batch_tune;
+
+/* Create a batch of count (1..4096) runs from descs[0..count-1]: every
+ * descriptor must have ndim 2, num_fluids 2, recon MFC_RECON_WENO5 and the
+ * same precision; n[0], n[1] in [3, 32768]; other fields as for
+ * mfc_init_grid (kernel is ignored).  Allocates the stage registers on the
+ * current device.  MFC_E_ARG / MFC_E_UNSUPPORTED / MFC_E_NOMEM with *out
+ * set to NULL on failure.  The initial configuration is {0, 1, 1}. */
+int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out);
+
+/* Release the batch (waits for the device). */
+int mfc_batch_free(mfc_batch *b);
+
+/* State layout of run `run` (host only): nvar, padded sizes, element size. */
+int mfc_batch_layout(const mfc_batch *b, int run, int64_t *nvar, int64_t padded[3], int64_t *elem_bytes);
+
+/* Total interior cells and number of runs (host only). */
+int mfc_batch_cells(const mfc_batch *b, int64_t *cells, int *nrun);
+
+/* One SSP-RK3 step of every run in place on q[0..count-1] (device arrays of
+ * the run layouts; ghost cells are filled by the step).  Step size per run:
+ * cfl * min_d dx_d / (max wave speed of that run), on the device. */
+int mfc_batch_step(mfc_batch *b, void *const *q, double cfl, void *stream);
+
+/* nsteps steps.  With use_graph != 0, steps are replayed from a HIP graph
+ * that captures up to 64 steps of the whole ensemble; it is captured on the
+ * first call and reused while q, cfl, the chunk length and the
+ * configuration stay the same.  Kernel timing (mfc_batch_set_timing) turns
+ * graph replay off. */
+int mfc_batch_run(mfc_batch *b, void *const *q, int nsteps, double cfl, int use_graph, void *stream);
+
+/* Choose the launch configuration: time the first-stage kernel (which reads
+ * q and writes only a stage register, so states and times are unchanged;
+ * ghost cells of q are refilled) reps (1..1000) times for each of the
+ * 3 x 3 x 2 configurations, keep the fastest and return it in *best.
+ * ms_table (nullable, 18 doubles) receives the mean time of configuration
+ * (shape, groups, xcd) at index (shape * 3 + groups) * 2 + xcd.
+ * Synchronises. */
+int mfc_batch_autotune(mfc_batch *b, void *const *q, int reps, mfc_batch_tune *best, double *ms_table, void *stream);
+int mfc_batch_set_tune(mfc_batch *b, const mfc_batch_tune *t);
+int mfc_batch_get_tune(const mfc_batch *b, mfc_batch_tune *t);
+
+/* Kernel timing of the batched right-hand-side launches (HIP events on the
+ * launch stream), as mfc_set_kernel_timing / mfc_kernel_time. */
+int mfc_batch_set_timing(mfc_batch *b, int enable);
+int mfc_batch_kernel_time(mfc_batch *b, double *ms_total, int64_t *launches);
+
+/* Synchronise and read the accumulated simulated time of every run into
+ * t_host[0..count-1]. */
+int mfc_batch_time(mfc_batch *b, double *t_host, void *stream);
+
+/* Synchronise; MFC_E_NONPHYSICAL if any run met a non-physical cell since
+ * the last check (the flag is then cleared). */
+int mfc_batch_check(mfc_batch *b, void *stream);
+
 /* Message for a status code (static storage). */
 const char *mfc_strerror(int status);
 

@@ -40,6 +40,13 @@ class mfc_grid_desc(ctypes.Structure):
                 ("recon", ctypes.c_int), ("weno_eps", ctypes.c_double), ("kernel", ctypes.c_int)]
 
 
+class mfc_batch_tune(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int), ("groups", ctypes.c_int), ("xcd", ctypes.c_int)]
+
+
+BATCH_SHAPES = ((16, 16), (32, 8), (64, 4))
+BATCH_GROUPS_PER_CU = (1, 2, 4)
+
 _lib = None
 _VP = ctypes.c_void_p
 _SIGNATURES = {
@@ -59,6 +66,21 @@ _SIGNATURES = {
     "mfc_check": [_VP, _VP],
     "mfc_set_kernel_timing": [_VP, ctypes.c_int],
     "mfc_kernel_time": [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "mfc_batch_init": [ctypes.POINTER(mfc_grid_desc), ctypes.c_int, ctypes.POINTER(_VP)],
+    "mfc_batch_free": [_VP],
+    "mfc_batch_layout": [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                         ctypes.POINTER(ctypes.c_int64)],
+    "mfc_batch_cells": [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)],
+    "mfc_batch_step": [_VP, ctypes.POINTER(_VP), ctypes.c_double, _VP],
+    "mfc_batch_run": [_VP, ctypes.POINTER(_VP), ctypes.c_int, ctypes.c_double, ctypes.c_int, _VP],
+    "mfc_batch_autotune": [_VP, ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(mfc_batch_tune),
+                           ctypes.POINTER(ctypes.c_double), _VP],
+    "mfc_batch_set_tune": [_VP, ctypes.POINTER(mfc_batch_tune)],
+    "mfc_batch_get_tune": [_VP, ctypes.POINTER(mfc_batch_tune)],
+    "mfc_batch_set_timing": [_VP, ctypes.c_int],
+    "mfc_batch_kernel_time": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "mfc_batch_time": [_VP, ctypes.POINTER(ctypes.c_double), _VP],
+    "mfc_batch_check": [_VP, _VP],
 }
 
 
@@ -268,3 +290,142 @@ class Solver:
 
     def check(self):
         mfc_check(self.h)
+
+
+# ---------------------------------------------------------------------------
+# Batched ensembles of 2D runs
+# ---------------------------------------------------------------------------
+
+def _ptr_array(qs):
+    return (_VP * len(qs))(*[q.data_ptr() for q in qs])
+
+
+def mfc_batch_init(descs) -> ctypes.c_void_p:
+    arr = (mfc_grid_desc * len(descs))(*descs)
+    h = _VP()
+    _check(lib().mfc_batch_init(arr, len(descs), ctypes.byref(h)), "mfc_batch_init")
+    return h
+
+
+def mfc_batch_free(b):
+    _check(lib().mfc_batch_free(b), "mfc_batch_free")
+
+
+def mfc_batch_layout(b, run: int):
+    nv, eb = ctypes.c_int64(), ctypes.c_int64()
+    pad = (ctypes.c_int64 * 3)()
+    _check(lib().mfc_batch_layout(b, run, ctypes.byref(nv), pad, ctypes.byref(eb)), "mfc_batch_layout")
+    return nv.value, tuple(pad), eb.value
+
+
+def mfc_batch_cells(b):
+    c, n = ctypes.c_int64(), ctypes.c_int()
+    _check(lib().mfc_batch_cells(b, ctypes.byref(c), ctypes.byref(n)), "mfc_batch_cells")
+    return c.value, n.value
+
+
+def mfc_batch_step(b, qs, cfl: float, stream=None):
+    _check(lib().mfc_batch_step(b, _ptr_array(qs), cfl, _stream(stream)), "mfc_batch_step")
+
+
+def mfc_batch_run(b, qs, nsteps: int, cfl: float, use_graph: bool = True, stream=None):
+    _check(lib().mfc_batch_run(b, _ptr_array(qs), nsteps, cfl, int(use_graph), _stream(stream)), "mfc_batch_run")
+
+
+def mfc_batch_autotune(b, qs, reps: int = 5, stream=None):
+    best = mfc_batch_tune()
+    table = (ctypes.c_double * 18)()
+    _check(lib().mfc_batch_autotune(b, _ptr_array(qs), reps, ctypes.byref(best), table, _stream(stream)),
+           "mfc_batch_autotune")
+    return (best.shape, best.groups, best.xcd), list(table)
+
+
+def mfc_batch_set_tune(b, shape: int, groups: int, xcd: int):
+    t = mfc_batch_tune(shape, groups, xcd)
+    _check(lib().mfc_batch_set_tune(b, ctypes.byref(t)), "mfc_batch_set_tune")
+
+
+def mfc_batch_get_tune(b):
+    t = mfc_batch_tune()
+    _check(lib().mfc_batch_get_tune(b, ctypes.byref(t)), "mfc_batch_get_tune")
+    return t.shape, t.groups, t.xcd
+
+
+def mfc_batch_set_timing(b, enable: bool):
+    _check(lib().mfc_batch_set_timing(b, int(enable)), "mfc_batch_set_timing")
+
+
+def mfc_batch_kernel_time(b):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().mfc_batch_kernel_time(b, ctypes.byref(ms), ctypes.byref(n)), "mfc_batch_kernel_time")
+    return ms.value, n.value
+
+
+def mfc_batch_time(b, nrun: int, stream=None):
+    t = (ctypes.c_double * nrun)()
+    _check(lib().mfc_batch_time(b, t, _stream(stream)), "mfc_batch_time")
+    return list(t)
+
+
+def mfc_batch_check(b, stream=None):
+    _check(lib().mfc_batch_check(b, _stream(stream)), "mfc_batch_check")
+
+
+class Batch:
+    """A batch handle for a list of 2D GridSpecs plus torch state helpers."""
+
+    def __init__(self, specs, precision: int = MFC_FP32_MIXED):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible; the library runs on the GPU only")
+        self.specs = list(specs)
+        self.b = mfc_batch_init([make_desc(s, precision) for s in self.specs])
+        self.cells, self.nrun = mfc_batch_cells(self.b)
+        self.shapes = []
+        for r in range(self.nrun):
+            nv, pad, eb = mfc_batch_layout(self.b, r)
+            self.shapes.append((nv, pad[2], pad[1], pad[0]))
+        self.dtype = torch.float64 if eb == 8 else torch.float32
+        self.precision = precision
+
+    def close(self):
+        if self.b:
+            mfc_batch_free(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def states_from_prim(self, ws):
+        """Device states from host primitive arrays, converted on the GPU by
+        single-grid handles of the same runs."""
+        qs = []
+        for spec, w in zip(self.specs, ws):
+            s = Solver(spec, precision=self.precision)
+            qs.append(s.state_from_prim(w))
+            s.close()
+        return qs
+
+    def step(self, qs, cfl):
+        mfc_batch_step(self.b, qs, cfl)
+
+    def run(self, qs, nsteps, cfl, use_graph=True):
+        mfc_batch_run(self.b, qs, nsteps, cfl, use_graph)
+
+    def autotune(self, qs, reps=5):
+        return mfc_batch_autotune(self.b, qs, reps)
+
+    def set_tune(self, shape, groups, xcd):
+        mfc_batch_set_tune(self.b, shape, groups, xcd)
+
+    def tune(self):
+        return mfc_batch_get_tune(self.b)
+
+    def time(self):
+        return mfc_batch_time(self.b, self.nrun)
+
+    def check(self):
+        mfc_batch_check(self.b)

@@ -230,10 +230,11 @@ def normal_shock_air(mach: float, p1: float = 1.0e5, rho1: float = 1.2, gamma: f
     return p2, rho2, u2, ws
 
 
-def droplet_shock_2d(n: int, seed: int, mach: float = 1.5, x_shock: float = 0.1):
+def droplet_shock_2d(n, seed: int, mach: float = 1.5, x_shock: float = 0.1):
     """2D water droplets (1-8, radii U[0.05, 0.15], centres U([0.3, 0.9] x
     [0.1, 0.9]), non-overlapping) in air at 1e5 Pa, struck by a Mach-1.5
-    air shock at x = 0.1 moving in +x, on the unit square."""
+    air shock at x = 0.1 moving in +x, on the unit square; n cells per side
+    (an int) or (nx, ny)."""
     rng = np.random.default_rng(seed)
     ndrop = int(rng.integers(1, 9))
     centres, radii = [], []
@@ -245,12 +246,12 @@ def droplet_shock_2d(n: int, seed: int, mach: float = 1.5, x_shock: float = 0.1)
         if all(np.linalg.norm(c - c2) >= r + r2 for c2, r2 in zip(centres, radii)):
             centres.append(c)
             radii.append(r)
-    spec = GridSpec(ndim=2, n=(n, n))
+    spec = GridSpec(ndim=2, n=(n, n) if isinstance(n, (int, np.integer)) else tuple(n))
     x, y, _ = spec.mesh()
     dist = np.full(np.broadcast(x, y).shape, np.inf)
     for c, r in zip(centres, radii):
         dist = np.minimum(dist, np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2) - r)
-    water = _smooth_step(-dist, spec.dx[0])  # 1 inside droplets
+    water = _smooth_step(-dist, max(spec.dx[:2]))  # 1 inside droplets, smeared over the coarser spacing
     alpha1 = ALPHA_MIN + (1.0 - 2.0 * ALPHA_MIN) * water
     p2, rho2, u2, _ = normal_shock_air(mach)
     behind = _smooth_step(x_shock - x, spec.dx[0]) * np.ones_like(water)

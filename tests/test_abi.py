@@ -77,3 +77,53 @@ def test_null_arguments(L):
     assert L.mfc_rhs(None, None, None, None) == mfc.MFC_E_ARG
     assert L.mfc_rk3_step(None, None, 0.3, 0.0, None) == mfc.MFC_E_ARG
     assert L.mfc_free_grid(None) == mfc.MFC_OK
+
+
+def batch_descs(count=3, **kw):
+    out = []
+    for r in range(count):
+        spec = W.GridSpec(ndim=2, n=(16 + 8 * r, 24))
+        d = mfc.make_desc(spec, precision=mfc.MFC_FP32_MIXED)
+        out.append(d)
+    for k, v in kw.items():
+        d = out[-1]
+        if isinstance(v, (list, tuple)):
+            arr = getattr(d, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(d, k, v)
+    return (mfc.mfc_grid_desc * count)(*out)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ndim=3), mfc.MFC_E_UNSUPPORTED),
+    (dict(ndim=1), mfc.MFC_E_UNSUPPORTED),
+    (dict(precision=mfc.MFC_FP64), mfc.MFC_E_ARG),   # mixed precisions in one batch
+    (dict(num_fluids=3), mfc.MFC_E_UNSUPPORTED),
+    (dict(recon=mfc.MFC_RECON_LEARNED), mfc.MFC_E_UNSUPPORTED),
+    (dict(n=(2, 24, 1)), mfc.MFC_E_ARG),
+    (dict(n=(40000, 24, 1)), mfc.MFC_E_ARG),
+    (dict(gamma=(0.9, 1.4)), mfc.MFC_E_ARG),
+    (dict(bc=(1, 0, 0, 0, 0, 0)), mfc.MFC_E_ARG),
+    (dict(hi=(0.0, 1.0, 1.0)), mfc.MFC_E_ARG),
+    (dict(weno_eps=-1.0), mfc.MFC_E_ARG),
+])
+def test_batch_init_rejects_invalid_descriptors(L, kw, code):
+    b = ctypes.c_void_p(123)
+    assert L.mfc_batch_init(batch_descs(**kw), 3, ctypes.byref(b)) == code
+    assert b.value is None
+
+
+def test_batch_null_arguments(L):
+    b = ctypes.c_void_p()
+    assert L.mfc_batch_init(None, 3, ctypes.byref(b)) == mfc.MFC_E_ARG
+    assert L.mfc_batch_init(batch_descs(), 0, ctypes.byref(b)) == mfc.MFC_E_ARG
+    assert L.mfc_batch_init(batch_descs(), 3, None) == mfc.MFC_E_ARG
+    assert L.mfc_batch_step(None, None, 0.3, None) == mfc.MFC_E_ARG
+    assert L.mfc_batch_run(None, None, 1, 0.3, 1, None) == mfc.MFC_E_ARG
+    assert L.mfc_batch_autotune(None, None, 1, None, None, None) == mfc.MFC_E_ARG
+    assert L.mfc_batch_set_tune(None, None) == mfc.MFC_E_ARG
+    assert L.mfc_batch_check(None, None) == mfc.MFC_E_ARG
+    assert L.mfc_batch_time(None, None, None) == mfc.MFC_E_ARG
+    assert L.mfc_batch_free(None) == mfc.MFC_OK
