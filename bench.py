@@ -48,9 +48,30 @@ BYTES_PER_CELL_UPDATE = (112 + 168 + 168) / 3
 SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences)", flops=1601, bytes=56 + 64),
          1: dict(name="k_z (z reconstruction, HLLC, source, stage update)", flops=2416 - 1601,
                  bytes=56 + 64 + 56 * 2 / 3 + 56)}
+# Measured HBM traffic per launch (bytes) of the split path's kernels on the
+# 128^3 FP64 bubble: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each
+# scaled by its reading for a copy kernel of known size (FETCH_SIZE x 2.00,
+# WRITE_SIZE x 1.00).  Valid only for the kernel sources they were taken on;
+# any change to those files turns `traffic` back to null.
+TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h")
+TRAFFIC = {"sha256": "23e7f59b1a95a42e8f73d28a039d6506b28fada1b7a917c036418b517b797690",
+           ("split", "fp64", 128, 0): (275.87e6, 167.77e6),
+           ("split", "fp64", 128, 1): (651.10e6, 127.40e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
+
+
+def measured_traffic(kernel, precision, n, slot):
+    """(read, write) HBM bytes per launch from the counter runs, or None."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_09163_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sha256"]:
+        return None
+    return TRAFFIC.get((kernel, precision, n, slot))
 
 
 def cpu_baseline(spec, w):
@@ -150,6 +171,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["bubble", "ensemble"], default="bubble",
                     help="bubble: the 3D bubble collapse (default); ensemble: 64 uneven 2D droplet-shock runs")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the run, scale-copy MIB MiB of float64 three times (a kernel of known HBM "
+                         "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -196,7 +220,7 @@ def main():
 
     updates = spec.cells * 3 * args.steps
     value = updates / elapsed
-    def roofline(ms, n, name, flops, nbytes):
+    def roofline(ms, n, name, flops, nbytes, slot=0):
         avg = ms / 1e3 / max(n, 1)
         achieved = flops * spec.cells / avg
         hbm = nbytes * spec.cells / avg
@@ -205,6 +229,12 @@ def main():
              "frac": achieved / PEAK_FP64_VALU, "traffic": None}
         if bound == "hbm":
             r.update(achieved=hbm / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=hbm / PEAK_HBM)
+        tr = measured_traffic(args.kernel, args.precision, args.n, slot)
+        if tr:
+            # measured HBM bytes per launch over the same average launch duration
+            r.update(traffic=sum(tr) / avg / 1e9, traffic_unit="GB/s",
+                     traffic_bytes_per_launch={"read": tr[0], "write": tr[1]},
+                     traffic_vs_algorithmic=sum(tr) / (nbytes * spec.cells))
         r.update({"kernel": name, "launches": n, "avg_launch_us": avg * 1e6, "flops_per_cell_update": flops,
                   "bytes_per_cell_update": nbytes, "fp64_TFLOPs": achieved / 1e12, "fp64_frac": achieved / PEAK_FP64_VALU,
                   "hbm_algorithmic_GBps": hbm / 1e9, "hbm_frac": hbm / PEAK_HBM})
@@ -212,7 +242,7 @@ def main():
 
     if args.kernel == "split":
         roof = roofline(ms_kernel, launches, SPLIT[0]["name"], SPLIT[0]["flops"], SPLIT[0]["bytes"])
-        roof_z = roofline(ms_kernel1, launches1, SPLIT[1]["name"], SPLIT[1]["flops"], SPLIT[1]["bytes"])
+        roof_z = roofline(ms_kernel1, launches1, SPLIT[1]["name"], SPLIT[1]["flops"], SPLIT[1]["bytes"], slot=1)
     else:
         name = "k_fused<3> (fused RHS + stage update)" if args.kernel == "fused" else "staged RHS sequence"
         roof = roofline(ms_kernel, launches, name, FLOPS_PER_CELL_UPDATE, BYTES_PER_CELL_UPDATE)
@@ -231,6 +261,16 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, w)
     print(json.dumps(out), flush=True)
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
+
+
+def copy_probe(torch, mib):
+    a = torch.ones(mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
