@@ -40,7 +40,8 @@ def build(force: bool = True) -> str:
 class _Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3),
                 ("gamma", ctypes.c_double * 2), ("pi_inf", ctypes.c_double * 2), ("bc", ctypes.c_int * 6),
-                ("weno_eps", ctypes.c_double)]
+                ("weno_eps", ctypes.c_double), ("recon", ctypes.c_int),
+                ("smooth", ctypes.POINTER(ctypes.c_ubyte))]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -83,8 +84,18 @@ def lib():
     return _lib
 
 
-def grid(spec) -> _Grid:
+RECON_WENO5, RECON_LINEAR, RECON_MASK = 0, 1, 2
+
+
+def grid(spec, recon: int = RECON_WENO5, smooth=None) -> _Grid:
+    """C grid descriptor.  recon RECON_MASK needs `smooth`, a uint8 array
+    [ndim, *padded shape] (kept alive by the caller while the grid is used)."""
     g = _Grid()
+    g.recon = recon
+    if recon == RECON_MASK:
+        assert smooth is not None and smooth.dtype == np.uint8 and smooth.flags["C_CONTIGUOUS"]
+        assert smooth.shape == (spec.ndim,) + spec.shape[1:]
+        g.smooth = smooth.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
     g.ndim = spec.ndim
     for d in range(3):
         g.n[d] = spec.n[d] if d < spec.ndim else 1
@@ -182,12 +193,15 @@ def fill_ghosts(spec, q):
     return q
 
 
-def rhs(spec, q):
-    """(dq/dt on interior cells (ghost entries zero), status); q must have ghosts filled."""
+def rhs(spec, q, recon: int = RECON_WENO5, smooth=None):
+    """(dq/dt on interior cells (ghost entries zero), status); q must have
+    ghosts filled.  recon/smooth select the reconstruction (see grid)."""
     q = _arr(q)
     assert q.shape == spec.shape
     out = np.zeros_like(q)
-    st = lib().ora_rhs(ctypes.byref(grid(spec)), _ptr(q), _ptr(out))
+    if smooth is not None:
+        smooth = np.ascontiguousarray(smooth, dtype=np.uint8)
+    st = lib().ora_rhs(ctypes.byref(grid(spec, recon, smooth)), _ptr(q), _ptr(out))
     return out, st
 
 
@@ -213,9 +227,11 @@ def rk3_step(spec, q, dt: float):
     return q, st
 
 
-def run(spec, q, nsteps: int, cfl: float = 0.0, dt: float = 0.0):
-    """(q after nsteps steps, total time, status); CFL time step if cfl > 0."""
+def run(spec, q, nsteps: int, cfl: float = 0.0, dt: float = 0.0, recon: int = RECON_WENO5):
+    """(q after nsteps steps, total time, status); CFL time step if cfl > 0.
+    recon RECON_LINEAR runs the linear fifth-order scheme everywhere."""
+    assert recon in (RECON_WENO5, RECON_LINEAR)
     q = _arr(q).copy()
     t = ctypes.c_double()
-    st = lib().ora_run(ctypes.byref(grid(spec)), _ptr(q), nsteps, cfl, dt, ctypes.byref(t))
+    st = lib().ora_run(ctypes.byref(grid(spec, recon)), _ptr(q), nsteps, cfl, dt, ctypes.byref(t))
     return q, t.value, st

@@ -58,6 +58,12 @@ typedef struct {
     double pi_inf[2];   /* stiffened-gas pi_infinity of fluids 1 and 2    */
     int bc[6];          /* x-,x+,y-,y+,z-,z+: 0 extrapolation, 1 periodic */
     double weno_eps;    /* WENO5-JS epsilon                               */
+    int recon;          /* 0 WENO5 everywhere; 1 the linear fifth-order
+                           stencil everywhere; 2 per (cell, direction) as
+                           `smooth` says                                   */
+    const unsigned char *smooth; /* recon 2: smooth[d * padded cells + c]
+                           != 0 selects the linear stencil for every
+                           variable of padded cell c along direction d    */
 } ora_grid;
 
 int ora_nvar(int ndim) { return 4 + ndim; }
@@ -413,7 +419,15 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                             c[d] = cell - 2 + t;
                             s[t] = w[at(g, v, c[0], c[1], c[2])];
                         }
-                        ora_weno5(s, g->weno_eps, &rp[(cell + 1) * nv + v], &rm[(cell + 1) * nv + v], NULL);
+                        int lin = g->recon == 1;
+                        if (g->recon == 2) {
+                            c[d] = cell;
+                            lin = g->smooth[(int64_t)d * ora_padded_cells(g) + at(g, 0, c[0], c[1], c[2])] != 0;
+                        }
+                        if (lin)
+                            ora_linear5(s, &rp[(cell + 1) * nv + v], &rm[(cell + 1) * nv + v]);
+                        else
+                            ora_weno5(s, g->weno_eps, &rp[(cell + 1) * nv + v], &rm[(cell + 1) * nv + v], NULL);
                     }
                 /* Riemann problems at faces f - 1/2, f = 0 .. n: left state
                  * from cell f-1 (its + face), right state from cell f */
