@@ -74,6 +74,35 @@ def measured_traffic(kernel, precision, n, slot):
     return TRAFFIC.get((kernel, precision, n, slot))
 
 
+def error_vs_reference(spec, w, make_solver, steps, mfc, weights, tau):
+    """Relative L1 density error of this form against the FP64 WENO5 path
+    (the path the parity tests check against the oracle) after `steps`
+    steps of one fixed dt (CFL 0.3 of the initial state) from the same
+    initial state; with a network, also the share of interior (cell,
+    direction) reconstructions it routes to the linear stencil at the end."""
+    ref = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_SPLIT, precision=mfc.MFC_FP64)
+    qr = ref.state_from_prim(w)
+    dt = 0.3 * min(spec.dx[:spec.ndim]) / ref.max_wavespeed(qr)
+    ref.run(qr, steps, dt=dt)
+    ref.check()
+    s = make_solver()
+    q = s.state_from_prim(w)
+    s.run(q, steps, dt=dt)
+    s.check()
+    I = (slice(None),) + spec.interior[1:]
+    rho_r = (qr[0] + qr[1])[I[1:]].double()
+    rho = (q[0] + q[1])[I[1:]].double()
+    out = {"rel_l1_density": float((rho - rho_r).abs().sum() / rho_r.abs().sum()), "steps": steps, "dt": dt,
+           "reference": "FP64 WENO5 split path (parity-tested against the oracle)"}
+    if weights is not None:
+        X, Y, _ = ref.harvest(q.double().contiguous())
+        t = mfc.Trainer(1)
+        t.set_params(weights)
+        P = t.infer(X)
+        out.update(routed_to_linear=float((P > tau).float().mean()), labelled_smooth=float(Y.float().mean()))
+    return out
+
+
 def cpu_baseline(spec, w):
     import oracle
 
@@ -171,6 +200,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["bubble", "ensemble"], default="bubble",
                     help="bubble: the 3D bubble collapse (default); ensemble: 64 uneven 2D droplet-shock runs")
+    ap.add_argument("--recon", choices=["weno5", "learned"], default="weno5",
+                    help="learned: reconstruction routed by the trained indicator (weights from --weights)")
+    ap.add_argument("--tau", type=float, default=0.5, help="routing threshold on P(smooth)")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2305_09163_amd", "indicator_weights.npy"))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, scale-copy MIB MiB of float64 three times (a kernel of known HBM "
                          "traffic that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -192,7 +225,23 @@ def main():
     spec, w = W.bubble_collapse_3d(n=args.n)
     kernel = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}[args.kernel]
     precision = mfc.MFC_FP64 if args.precision == "fp64" else mfc.MFC_FP32_MIXED
-    solver = mfc.Solver(spec, kernel=kernel, precision=precision)
+    learned = args.recon == "learned"
+    weights = None
+    if learned:
+        import numpy as np
+        if not os.path.exists(args.weights):
+            sys.exit(f"bench.py: {args.weights} not found; train it with "
+                     "`python -m paper_2305_09163_amd.train_indicator`")
+        weights = np.load(args.weights, allow_pickle=False)
+
+    def make_solver():
+        s = mfc.Solver(spec, kernel=kernel, precision=precision,
+                       recon=mfc.MFC_RECON_LEARNED if learned else mfc.MFC_RECON_WENO5)
+        if learned:
+            s.set_indicator(weights, args.tau)
+        return s
+
+    solver = make_solver()
     q = solver.state_from_prim(w)
     cfl = 0.3
     for _ in range(args.warmup):
@@ -253,11 +302,15 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
            "data": "synthetic",
            "config": {"workload": f"bubble_collapse_3d_{args.n}", "cells": spec.cells, "nvar": spec.nvar,
-                      "cfl": cfl, "precision": args.precision, "kernel": args.kernel, "recon": "weno5",
+                      "cfl": cfl, "precision": args.precision, "kernel": args.kernel, "recon": args.recon,
                       "parallelism": "single GPU"},
            "roofline": roof, "simulated_time_s": t}
+    if learned:
+        out["config"]["tau"] = args.tau
     if roof_z:
         out["roofline_second_kernel"] = roof_z
+    if args.precision == "fp32" or learned:
+        out["error_vs_fp64_weno5"] = error_vs_reference(spec, w, make_solver, args.steps, mfc, weights, args.tau)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, w)
     print(json.dumps(out), flush=True)

@@ -80,7 +80,9 @@ typedef struct {
     int bc[6];           /* per face x-, x+, y-, y+, z-, z+: MFC_BC_*; periodic
                             must be set on both faces of a dimension               */
     int precision;       /* MFC_FP64 or MFC_FP32_MIXED                             */
-    int recon;           /* MFC_RECON_WENO5 (MFC_RECON_LEARNED: see mfc_set_indicator) */
+    int recon;           /* MFC_RECON_WENO5, or MFC_RECON_LEARNED (fused and split
+                            kernels; needs mfc_set_indicator before any
+                            right-hand side)                                       */
     double weno_eps;     /* WENO5-JS epsilon, > 0 (1e-6 in the paper's setting)    */
     int kernel;          /* MFC_KERNEL_*                                           */
 } mfc_grid_desc;
@@ -153,6 +155,70 @@ int mfc_check(mfc_grid *g, void *stream);
  * it, and resets them.  slot outside [0, 1] gives MFC_E_ARG. */
 int mfc_set_kernel_timing(mfc_grid *g, int enable);
 int mfc_kernel_time(mfc_grid *g, int slot, double *ms_total, int64_t *launches);
+
+/* ------------------------------------------------------------------------
+ * Learned smoothness indicator (project extension beside the WENO5
+ * reconstruction of Sec. 3.2).  For every (cell, direction) a perceptron
+ * 15 -> 32 -> 32 -> 1 (GELU, logistic output) reads the 5-cell stencils of
+ * alpha1, rho = a1r1 + a2r2 and p, each as (v_j - v_centre) /
+ * max(max_j |v_j - v_centre|, sqrt(weno_eps)), and gives P(smooth).  With
+ * MFC_RECON_LEARNED, a (cell, direction) with P(smooth) > tau takes the
+ * linear fifth-order stencil (the ideal-weight limit of WENO5) for every
+ * variable and both faces; all others take WENO5.  Products run on bf16
+ * matrix cores: their operands (inputs, W1, W2, hidden activations and,
+ * in training, the back-propagated dZ2 and dZ1) are rounded to bf16
+ * (nearest, ties to even), sums and all element-wise work are FP32.
+ *
+ * Parameters are 1601 floats in the flat order W1[15][32] (input-major),
+ * b1[32], W2[32][32] (input-major), b2[32], W3[32], b3.  Features are
+ * 16 bf16 values per sample (uint16_t bit patterns; the 16th is 0).
+ * ------------------------------------------------------------------------ */
+typedef struct mfc_trainer mfc_trainer;
+
+/* Install a network (1601 host floats, copied) and the routing threshold
+ * tau for the handle's MFC_RECON_LEARNED right-hand sides.  tau <= 0 routes
+ * every reconstruction to the linear stencil, tau >= 1 none.  MFC_E_ARG on
+ * non-finite parameters or tau. */
+int mfc_set_indicator(mfc_grid *g, const float *params_host, double tau);
+
+/* Training samples from an FP64 state q (device, the handle's layout; its
+ * ghost cells are refilled first, as mfc_fill_ghosts): for every interior
+ * (cell, direction), ordered direction-major then z, y, x, the 16 features
+ * (features[16 * sample ..], device) and the label (labels[sample], device):
+ * 1 when every variable's WENO5 weights stay within 0.01 of the ideal
+ * weights (max over the three stencils and both faces of |omega_r - d_r|)
+ * and 0 otherwise.  maxdev (nullable, device, doubles) receives that largest
+ * deviation.  Arrays hold ndim * cells samples.  MFC_E_UNSUPPORTED for an
+ * FP32 handle. */
+int mfc_harvest(mfc_grid *g, void *q, uint16_t *features, uint8_t *labels, double *maxdev, void *stream);
+
+/* A trainer owns FP32 master weights, Adam moments and gradient scratch for
+ * batches of up to max_batch samples (1 .. 2^31).  Weights start at 0:
+ * set them with mfc_trainer_set_params (which also clears the moments and
+ * the step count). */
+int mfc_trainer_init(int64_t max_batch, mfc_trainer **out);
+int mfc_trainer_free(mfc_trainer *t);
+int mfc_trainer_set_params(mfc_trainer *t, const float *params_host);   /* synchronises */
+int mfc_trainer_get_params(mfc_trainer *t, float *params_host);         /* synchronises */
+
+/* Gradient of the mean binary cross-entropy over `batch` samples (1 ..
+ * max_batch) of device arrays features / labels, sample i being
+ * index[i] (device int32, nullable: sample i is i).  The gradient and the
+ * mean loss stay on the device (deterministic: a fixed reduction order). */
+int mfc_trainer_grad(mfc_trainer *t, const uint16_t *features, const uint8_t *labels, const int32_t *index,
+                     int64_t batch, void *stream);
+
+/* Synchronise and copy the last gradient (1601 floats) and mean loss
+ * (nullable) to the host. */
+int mfc_trainer_read_grad(mfc_trainer *t, float *grad_host, float *loss_host, void *stream);
+
+/* One Adam step on the master weights with the last gradient:
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * w -= lr (m / (1 - b1^k)) / (sqrt(v / (1 - b2^k)) + eps), k = steps taken. */
+int mfc_trainer_adam(mfc_trainer *t, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* P(smooth) of n samples (device features -> device floats). */
+int mfc_trainer_infer(mfc_trainer *t, const uint16_t *features, int64_t n, float *prob, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched ensembles (project extension beside the method of Sec. 3).  Many

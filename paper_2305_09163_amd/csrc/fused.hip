@@ -16,7 +16,13 @@
 //   - each thread then forms its cell's flux differences plus the
 //     alpha1 div(u) source and the SSP-RK3 stage combination.
 // 2D uses the same tile without the z march; 1D uses a 256-cell row.
+// With ROUTE = true every (cell, direction) is first classified by the learned
+// indicator of mlp.h (whole wavefronts at a time) and a smooth one takes the
+// linear fifth-order stencil for every variable instead of WENO5.
+#include <type_traits>
+
 #include "internal.h"
+#include "mlp.h"
 
 namespace mfc {
 namespace {
@@ -60,16 +66,60 @@ __device__ __forceinline__ bool load_prim(const Grid &g, const T *__restrict__ q
     return bad && outside <= 1;
 }
 
+// Reconstruct one 5-cell stencil for all variables: WENO5, or the linear
+// stencil when lin is set.
+template <int NV, class T>
+__device__ __forceinline__ void recon_regs(const T (&zw)[5][NV], T eps, bool lin, T *plus, T *minus)
+{
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        if (lin) linear5_pair<T>(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], plus[v], minus[v]);
+        else weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, plus[v], minus[v]);
+    }
+}
+
+// The learned indicator's decision for a stencil held in registers (all lanes
+// of the wavefront must call).
 template <int NDIM, class T>
+__device__ __forceinline__ bool route_regs(const mlp::Params &P, uint16_t *scratch, const T (&zw)[5][4 + NDIM],
+                                           T sqrt_eps, float logit_tau, int lane)
+{
+    T av[5], rv[5], pv[5];
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+        av[j] = zw[j][3 + NDIM];
+        rv[j] = zw[j][0] + zw[j][1];
+        pv[j] = zw[j][2 + NDIM];
+    }
+    uint16_t f[16];
+    mlp::features<T>(av, rv, pv, sqrt_eps, f);
+    return mlp::smooth_wave(P, scratch, f, logit_tau, lane);
+}
+
+template <int NDIM, class T, bool ROUTE>
 __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
     k_fused(Grid g, const T *__restrict__ q, const T *q0, T *out, int mode, double dt,
-            const double *__restrict__ dt_dev, int *__restrict__ flag, int lz)
+            const double *__restrict__ dt_dev, int *__restrict__ flag, int lz, const float *__restrict__ mlpw,
+            float logit_tau, T sqrt_eps)
 {
     using S = Shape<NDIM>;
-    constexpr int NV = S::NV, A = 3 + NDIM, TX = S::TX, TY = S::TY, NT = S::NT, OY = S::OY;
+    constexpr int NV = S::NV, A = 3 + NDIM, E = 2 + NDIM, TX = S::TX, TY = S::TY, NT = S::NT, OY = S::OY;
     __shared__ T s_plane[NV][S::PY][S::PX];
     __shared__ T s_pair[2 * NV][S::NP];
-    __shared__ T s_flux[NV + 1][S::NF];
+    __shared__ __align__(16) T s_flux[NV + 1][S::NF];
+    // feature exchange area of the routed reconstruction (64 x 16 bf16 per
+    // wavefront): inside the flux array when it is large enough, since no
+    // thread reads the fluxes while reconstructions are formed
+    constexpr int kFeat = (NT / 64) * 64 * 16;
+    constexpr bool kInFlux = sizeof(T) * (NV + 1) * S::NF >= sizeof(uint16_t) * kFeat;
+    __shared__ __align__(16) typename std::conditional<ROUTE, mlp::Params, char>::type s_mlp;
+    __shared__ __align__(16) uint16_t s_feat_own[(ROUTE && !kInFlux) ? kFeat : 1];
+    uint16_t *scratch = (kInFlux ? (uint16_t *)&s_flux[0][0] : s_feat_own) + (threadIdx.x / 64) * 64 * 16;
+    const int lane = threadIdx.x % 64;
+    if constexpr (ROUTE) {
+        mlp::stage_params(s_mlp, nullptr, mlpw, threadIdx.x, NT);
+        __syncthreads();
+    }
     const T eps = T(g.eps), idx = T(g.inv_dx[0]), idy = T(g.inv_dx[1]), idz = T(g.inv_dx[2]);
 
     const int tid = threadIdx.x;
@@ -92,17 +142,17 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
     if constexpr (NDIM == 3) {
 #pragma unroll
         for (int p = 0; p < 5; p++) bad |= load_prim<NDIM, T>(g, q, cx, cy, z0 - 3 + p, zw[p]);
-        T plus_prev[NV], mk[NV], dummy;
-#pragma unroll
-        for (int v = 0; v < NV; v++)
-            weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, plus_prev[v], dummy);
+        T plus_prev[NV], mk[NV], dummy[NV];
+        bool lin = false;
+        if constexpr (ROUTE) lin = route_regs<NDIM, T>(s_mlp, scratch, zw, sqrt_eps, logit_tau, lane);
+        recon_regs<NV, T>(zw, eps, lin, plus_prev, dummy);
 #pragma unroll
         for (int p = 0; p < 4; p++)
 #pragma unroll
             for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
         bad |= load_prim<NDIM, T>(g, q, cx, cy, z0 + 2, zw[4]);
-#pragma unroll
-        for (int v = 0; v < NV; v++) weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, pk[v], mk[v]);
+        if constexpr (ROUTE) lin = route_regs<NDIM, T>(s_mlp, scratch, zw, sqrt_eps, logit_tau, lane);
+        recon_regs<NV, T>(zw, eps, lin, pk, mk);
         bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0), T>(g, plus_prev, mk, Fz, Fz[NV]) && own;
     }
 
@@ -121,10 +171,10 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
             bad |= load_prim<NDIM, T>(g, q, cx, cy, k + 3, zw[4]);
             T pn[NV], mn[NV];
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                wk[v] = zw[1][v];
-                weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, pn[v], mn[v]);
-            }
+            for (int v = 0; v < NV; v++) wk[v] = zw[1][v];
+            bool lin = false;
+            if constexpr (ROUTE) lin = route_regs<NDIM, T>(s_mlp, scratch, zw, sqrt_eps, logit_tau, lane);
+            recon_regs<NV, T>(zw, eps, lin, pn, mn);
             bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0), T>(g, pk, mn, Fzn, Fzn[NV]) && own;
 #pragma unroll
             for (int v = 0; v < NV; v++) pk[v] = pn[v];
@@ -156,13 +206,35 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
         __syncthreads();
 
         // ---- x: reconstruct cells -1 .. TX of every row
-        for (int p = tid; p < S::NPX; p += NT) {
-            const int row = p / (TX + 2), c = p % (TX + 2);
-            const int lj = row + OY;
+        if constexpr (ROUTE) {
+            for (int p0 = 0; p0 < S::NPX; p0 += NT) {  // uniform trip count: whole wavefronts classify
+                const int p = p0 + tid;
+                const bool valid = p < S::NPX;
+                const int pc = valid ? p : S::NPX - 1;
+                const int lj = pc / (TX + 2) + OY, c = pc % (TX + 2);
+                bool lin = false;
+                if (__ballot(valid))
+                    lin = mlp::smooth_stencil<T>(s_mlp, scratch, &s_plane[A][lj][c], &s_plane[0][lj][c],
+                                                 &s_plane[1][lj][c], &s_plane[E][lj][c], 1, sqrt_eps, logit_tau,
+                                                 lane);
+                if (valid) {
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                const T *s = &s_plane[v][lj][c];
-                weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                    for (int v = 0; v < NV; v++) {
+                        const T *s = &s_plane[v][lj][c];
+                        if (lin) linear5_pair<T>(s[0], s[1], s[2], s[3], s[4], s_pair[v][p], s_pair[NV + v][p]);
+                        else weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                    }
+                }
+            }
+        } else {
+            for (int p = tid; p < S::NPX; p += NT) {
+                const int row = p / (TX + 2), c = p % (TX + 2);
+                const int lj = row + OY;
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const T *s = &s_plane[v][lj][c];
+                    weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                }
             }
         }
         __syncthreads();
@@ -193,13 +265,42 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
 
         if constexpr (NDIM >= 2) {
             // ---- y: reconstruct rows -1 .. TY of every column
-            for (int p = tid; p < S::NPY; p += NT) {
-                const int c = p % TX, r = p / TX;
-                const int li = c + NG;
+            if constexpr (ROUTE) {
+                if constexpr (kInFlux) __syncthreads();  // x fluxes are read above before the area is reused
+                for (int p0 = 0; p0 < S::NPY; p0 += NT) {
+                    const int p = p0 + tid;
+                    const bool valid = p < S::NPY;
+                    const int pc = valid ? p : S::NPY - 1;
+                    const int li = pc % TX + NG, r = pc / TX;
+                    bool lin = false;
+                    if (__ballot(valid))
+                        lin = mlp::smooth_stencil<T>(s_mlp, scratch, &s_plane[A][r][li], &s_plane[0][r][li],
+                                                     &s_plane[1][r][li], &s_plane[E][r][li], S::PX, sqrt_eps,
+                                                     logit_tau, lane);
+                    if (valid) {
 #pragma unroll
-                for (int v = 0; v < NV; v++)
-                    weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li], s_plane[v][r + 3][li],
-                               s_plane[v][r + 4][li], eps, s_pair[v][p], s_pair[NV + v][p]);
+                        for (int v = 0; v < NV; v++) {
+                            if (lin)
+                                linear5_pair<T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                                s_plane[v][r + 3][li], s_plane[v][r + 4][li], s_pair[v][p],
+                                                s_pair[NV + v][p]);
+                            else
+                                weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                           s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, s_pair[v][p],
+                                           s_pair[NV + v][p]);
+                        }
+                    }
+                }
+            } else {
+                for (int p = tid; p < S::NPY; p += NT) {
+                    const int c = p % TX, r = p / TX;
+                    const int li = c + NG;
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                   s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, s_pair[v][p],
+                                   s_pair[NV + v][p]);
+                }
             }
             __syncthreads();
             for (int f = tid; f < S::NFY; f += NT) {
@@ -250,29 +351,31 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
     if (bad) atomicOr(flag, 1);
 }
 
-template <int NDIM, class T>
+template <int NDIM, class T, bool ROUTE>
 int rhs_fused(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s)
 {
     using S = Shape<NDIM>;
     const Grid &g = h->g;
     dim3 grid((g.n[0] + S::TX - 1) / S::TX, NDIM >= 2 ? (g.n[1] + S::TY - 1) / S::TY : 1,
               NDIM == 3 ? (g.n[2] + kLZ - 1) / kLZ : 1);
+    const T se = T(__builtin_sqrt(g.eps));
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_fused<NDIM, T>), grid, dim3(S::NT), 0, s, g, q, q0, out, mode, dt, dt_dev, h->flag, kLZ);
+    hipLaunchKernelGGL((k_fused<NDIM, T, ROUTE>), grid, dim3(S::NT), 0, s, g, q, q0, out, mode, dt, dt_dev, h->flag, kLZ,
+                       h->mlp, h->logit_tau, se);
     timing_end(h, s);
     return hip_status(hipGetLastError(), "fused right-hand side launch");
 }
 
-template <class T>
+template <class T, bool ROUTE>
 int rhs_fused_t(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt, const double *dt_dev,
                 hipStream_t s)
 {
     const T *a = (const T *)q, *b = (const T *)q0;
     T *o = (T *)out;
     switch (h->g.ndim) {
-    case 1: return rhs_fused<1, T>(h, a, b, o, mode, dt, dt_dev, s);
-    case 2: return rhs_fused<2, T>(h, a, b, o, mode, dt, dt_dev, s);
-    default: return rhs_fused<3, T>(h, a, b, o, mode, dt, dt_dev, s);
+    case 1: return rhs_fused<1, T, ROUTE>(h, a, b, o, mode, dt, dt_dev, s);
+    case 2: return rhs_fused<2, T, ROUTE>(h, a, b, o, mode, dt, dt_dev, s);
+    default: return rhs_fused<3, T, ROUTE>(h, a, b, o, mode, dt, dt_dev, s);
     }
 }
 
@@ -281,8 +384,13 @@ int rhs_fused_t(mfc_grid *h, const void *q, const void *q0, void *out, int mode,
 int launch_rhs_fused(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
                      const double *dt_dev, hipStream_t s)
 {
-    if (h->desc.precision == MFC_FP32_MIXED) return rhs_fused_t<float>(h, q, q0, out, mode, dt, dt_dev, s);
-    return rhs_fused_t<double>(h, q, q0, out, mode, dt, dt_dev, s);
+    const bool learned = h->desc.recon == MFC_RECON_LEARNED;
+    if (learned && !h->mlp) return fail(MFC_E_ARG, "MFC_RECON_LEARNED needs mfc_set_indicator first");
+    if (h->desc.precision == MFC_FP32_MIXED)
+        return learned ? rhs_fused_t<float, true>(h, q, q0, out, mode, dt, dt_dev, s)
+                       : rhs_fused_t<float, false>(h, q, q0, out, mode, dt, dt_dev, s);
+    return learned ? rhs_fused_t<double, true>(h, q, q0, out, mode, dt, dt_dev, s)
+                   : rhs_fused_t<double, false>(h, q, q0, out, mode, dt, dt_dev, s);
 }
 
 }  // namespace mfc

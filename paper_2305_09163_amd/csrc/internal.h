@@ -31,6 +31,8 @@ struct mfc_grid {
     double *partial = nullptr; // per-block maxima of the wave-speed reduction
     double *scalars = nullptr; // [0] smax, [1] dt, [2] t, [3] spare
     int *flag = nullptr;       // non-physical flag
+    float *mlp = nullptr;      // learned indicator parameters (FP32, flat order of mlp.h)
+    float logit_tau = 0.0f;    // routing threshold on the indicator's logit
 
     // kernel timing, per slot (0: main right-hand-side kernel, 1: z kernel)
     bool timing = false;

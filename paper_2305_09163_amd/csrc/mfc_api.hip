@@ -223,7 +223,8 @@ int validate(const mfc_grid_desc *d)
     if (d->precision == MFC_FP32_MIXED && d->kernel == MFC_KERNEL_STAGED)
         return fail(MFC_E_UNSUPPORTED, "the staged path is FP64 only");
     if (d->kernel == MFC_KERNEL_SPLIT && d->ndim != 3) return fail(MFC_E_UNSUPPORTED, "the split path is 3D only");
-    if (d->recon != MFC_RECON_WENO5) return fail(MFC_E_UNSUPPORTED, "only MFC_RECON_WENO5 is built in this version");
+    if (d->recon == MFC_RECON_LEARNED && d->kernel == MFC_KERNEL_STAGED)
+        return fail(MFC_E_UNSUPPORTED, "the staged path reconstructs with WENO5 only");
     return MFC_OK;
 }
 
@@ -323,7 +324,8 @@ int mfc_free_grid(mfc_grid *h)
     if (!h) return MFC_OK;
     (void)hipDeviceSynchronize();
     for (void *p : {(void *)h->stage_a, (void *)h->stage_b, (void *)h->prim, (void *)h->recp, (void *)h->recm,
-                    (void *)h->faces, (void *)h->lxy, (void *)h->partial, (void *)h->scalars, (void *)h->flag})
+                    (void *)h->faces, (void *)h->lxy, (void *)h->partial, (void *)h->scalars, (void *)h->flag,
+                    (void *)h->mlp})
         if (p) (void)hipFree(p);
     for (auto &ev : h->ev)
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);

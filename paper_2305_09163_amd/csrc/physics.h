@@ -199,6 +199,19 @@ __device__ __forceinline__ void weno5_pair(float vm2, float vm1, float v0, float
     minus = __builtin_fmaf(nm, sp * r, v0);
 }
 
+// The linear fifth-order upwind reconstruction (the ideal-weight limit of
+// WENO5 on smooth data), in the same increments over v0:
+//   60 (plus - v0)  = 11a - 2b + 24c - 3d,
+//   60 (minus - v0) = 3b - 24a - 11c + 2d.
+template <class T>
+__device__ __forceinline__ void linear5_pair(T vm2, T vm1, T v0, T vp1, T vp2, T &plus, T &minus)
+{
+    const T b = vm1 - vm2, a = v0 - vm1, c = vp1 - v0, d = vp2 - vp1;
+    const T k = T(1.0 / 60.0);
+    plus = fmaT(fmaT(T(11), a, fmaT(T(24), c, fmaT(T(-2), b, T(-3) * d))), k, v0);
+    minus = fmaT(fmaT(T(-24), a, fmaT(T(-11), c, fmaT(T(3), b, T(2) * d))), k, v0);
+}
+
 // The contact speed s* of the HLLC solver from the two sides' values.
 // FP64 for both storage types: numerator and denominator cancel at material
 // interfaces (equal pressures, opposite wave speeds).

@@ -17,8 +17,15 @@
 // Neither kernel carries the other's state, so each fits its registers
 // without spilling; the price is one round trip of 8 values per cell through
 // HBM.  Both kernels are instantiated for FP64 and for the FP32 storage form
-// (T = float; the x+y part is kept in the same type).
+// (T = float; the x+y part is kept in the same type), and with the routed
+// reconstruction (ROUTE = true): every (cell, direction) is first classified by
+// the learned indicator of mlp.h, a whole wavefront at a time, and a smooth
+// one takes the linear fifth-order stencil for every variable instead of
+// WENO5.
+#include <type_traits>
+
 #include "internal.h"
+#include "mlp.h"
 
 namespace mfc {
 namespace {
@@ -55,15 +62,34 @@ __device__ __forceinline__ bool load_prim3(const Grid &g, const T *__restrict__ 
     return bad && outside <= 1;
 }
 
-template <class T>
+// Feature exchange area of the routed reconstruction: 64 samples x 16 bf16
+// per wavefront.  It lives in the flux array, which no thread reads while
+// reconstructions are formed, when that array is large enough.
+constexpr int kFeatWords = (NT / 64) * 64 * 16;
+
+template <class T, bool ROUTE>
+struct RouteLds {
+    static constexpr bool in_flux = sizeof(T) * (7 + 1) * NF >= sizeof(uint16_t) * kFeatWords;
+    using P = typename std::conditional<ROUTE, mlp::Params, char>::type;
+    static constexpr int own_words = (ROUTE && !in_flux) ? kFeatWords : 1;
+};
+
+template <class T, bool ROUTE>
 __global__ void __launch_bounds__(NT, 2)
-    k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag)
+    k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag,
+         const float *__restrict__ mlpw, float logit_tau, T sqrt_eps)
 {
     constexpr int NV = 7;
+    using R = RouteLds<T, ROUTE>;
     __shared__ T s_plane[NV][PY][PX];
     __shared__ T s_pair[2 * NV][NP];
-    __shared__ T s_flux[NV + 1][NF];
+    __shared__ __align__(16) T s_flux[NV + 1][NF];
+    __shared__ __align__(16) typename R::P s_mlp;
+    __shared__ __align__(16) uint16_t s_feat_own[R::own_words];
     const T eps = T(g.eps);
+    const int lane = threadIdx.x % 64;
+    uint16_t *scratch = (R::in_flux ? (uint16_t *)&s_flux[0][0] : s_feat_own) + (threadIdx.x / 64) * 64 * 16;
+    if constexpr (ROUTE) mlp::stage_params(s_mlp, nullptr, mlpw, threadIdx.x, NT);  // visible after the first barrier
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -102,12 +128,34 @@ __global__ void __launch_bounds__(NT, 2)
         __syncthreads();
 
         // ---- x: reconstruct cells -1 .. TX of every row, then the faces
-        for (int p = tid; p < NPX; p += NT) {
-            const int row = p / (TX + 2), c = p % (TX + 2);
+        if constexpr (ROUTE) {
+            for (int p0 = 0; p0 < NPX; p0 += NT) {  // uniform trip count: whole wavefronts classify
+                const int p = p0 + tid;
+                const bool valid = p < NPX;
+                const int pc = valid ? p : NPX - 1;
+                const int row = pc / (TX + 2), c = pc % (TX + 2);
+                bool lin = false;
+                if (__ballot(valid))
+                    lin = mlp::smooth_stencil<T>(s_mlp, scratch, &s_plane[6][row + NG][c], &s_plane[0][row + NG][c],
+                                                 &s_plane[1][row + NG][c], &s_plane[5][row + NG][c], 1, sqrt_eps,
+                                                 logit_tau, lane);
+                if (valid) {
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                const T *s = &s_plane[v][row + NG][c];
-                weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                    for (int v = 0; v < NV; v++) {
+                        const T *s = &s_plane[v][row + NG][c];
+                        if (lin) linear5_pair<T>(s[0], s[1], s[2], s[3], s[4], s_pair[v][p], s_pair[NV + v][p]);
+                        else weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                    }
+                }
+            }
+        } else {
+            for (int p = tid; p < NPX; p += NT) {
+                const int row = p / (TX + 2), c = p % (TX + 2);
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const T *s = &s_plane[v][row + NG][c];
+                    weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                }
             }
         }
         __syncthreads();
@@ -136,13 +184,41 @@ __global__ void __launch_bounds__(NT, 2)
             divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * idx;
         }
         // ---- y: reconstruct rows -1 .. TY of every column, then the faces
-        for (int p = tid; p < NPY; p += NT) {
-            const int c = p % TX, r = p / TX;
-            const int li = c + NG;
+        if constexpr (ROUTE) {
+            if constexpr (R::in_flux) __syncthreads();  // the x fluxes above are read before the area is reused
+            for (int p0 = 0; p0 < NPY; p0 += NT) {
+                const int p = p0 + tid;
+                const bool valid = p < NPY;
+                const int pc = valid ? p : NPY - 1;
+                const int li = pc % TX + NG, r = pc / TX;
+                bool lin = false;
+                if (__ballot(valid))
+                    lin = mlp::smooth_stencil<T>(s_mlp, scratch, &s_plane[6][r][li], &s_plane[0][r][li],
+                                                 &s_plane[1][r][li], &s_plane[5][r][li], PX, sqrt_eps, logit_tau,
+                                                 lane);
+                if (valid) {
 #pragma unroll
-            for (int v = 0; v < NV; v++)
-                weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li], s_plane[v][r + 3][li],
-                           s_plane[v][r + 4][li], eps, s_pair[v][p], s_pair[NV + v][p]);
+                    for (int v = 0; v < NV; v++) {
+                        if (lin)
+                            linear5_pair<T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                            s_plane[v][r + 3][li], s_plane[v][r + 4][li], s_pair[v][p],
+                                            s_pair[NV + v][p]);
+                        else
+                            weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                       s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, s_pair[v][p],
+                                       s_pair[NV + v][p]);
+                    }
+                }
+            }
+        } else {
+            for (int p = tid; p < NPY; p += NT) {
+                const int c = p % TX, r = p / TX;
+                const int li = c + NG;
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li], s_plane[v][r + 3][li],
+                               s_plane[v][r + 4][li], eps, s_pair[v][p], s_pair[NV + v][p]);
+            }
         }
         __syncthreads();
         for (int f = tid; f < NFY; f += NT) {
@@ -183,16 +259,31 @@ __global__ void __launch_bounds__(NT, 2)
 // columns (64 consecutive x per wavefront: coalesced plane loads) and march
 // through kLZ planes, starting two planes early to reconstruct cell z0-1 and
 // solve face z0-1/2 without writing.
-template <class T>
+template <class T, bool ROUTE>
 __global__ void __launch_bounds__(kZX * kZY, 2)
     k_z(Grid g, const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ lxy, int mode, double dt,
-        const double *__restrict__ dt_dev, int *__restrict__ flag)
+        const double *__restrict__ dt_dev, int *__restrict__ flag, const float *__restrict__ mlpw, float logit_tau,
+        T sqrt_eps)
 {
     constexpr int NV = 7, A = 6;
     const T eps = T(g.eps), idz = T(g.inv_dx[2]);
-    const int gx = blockIdx.x * kZX + threadIdx.x % kZX;
-    const int gy = blockIdx.y * kZY + threadIdx.x / kZX;
-    if (gx >= g.n[0] || gy >= g.n[1]) return;   // no barriers in this kernel
+    int gx = blockIdx.x * kZX + threadIdx.x % kZX;
+    int gy = blockIdx.y * kZY + threadIdx.x / kZX;
+    const bool own = gx < g.n[0] && gy < g.n[1];
+    __shared__ __align__(16) typename std::conditional<ROUTE, mlp::Params, char>::type s_mlp;
+    __shared__ __align__(16) uint16_t s_feat[ROUTE ? kZX * kZY * 16 : 1];
+    if constexpr (ROUTE) {
+        // every lane of a wavefront takes part in the classification: lanes
+        // past a ragged edge march a duplicate of the last column
+        mlp::stage_params(s_mlp, nullptr, mlpw, threadIdx.x, kZX * kZY);
+        __syncthreads();
+        gx = min(gx, g.n[0] - 1);
+        gy = min(gy, g.n[1] - 1);
+    } else if (!own) {
+        return;   // no barriers in this variant
+    }
+    uint16_t *scratch = s_feat + (ROUTE ? (threadIdx.x / 64) * 64 * 16 : 0);
+    const int lane = threadIdx.x % 64;
     const int z0 = blockIdx.z * kLZ, z1 = min(z0 + kLZ, g.n[2]);
     const T hdt = T(mode ? (dt_dev ? *dt_dev : dt) : 0.0);
     const T ca = T(mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0));
@@ -212,13 +303,28 @@ __global__ void __launch_bounds__(kZX * kZY, 2)
             for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
         bad |= load_prim3<T>(g, q, gx, gy, k + 3, zw[4]);
         T pn[NV], mn[NV], Fzn[NV + 1];
+        bool lin = false;
+        if constexpr (ROUTE) {
+            T av[5], rv[5], pv[5];
 #pragma unroll
-        for (int v = 0; v < NV; v++)
-            weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, pn[v], mn[v]);
+            for (int j = 0; j < 5; j++) {
+                av[j] = zw[j][A];
+                rv[j] = zw[j][0] + zw[j][1];
+                pv[j] = zw[j][5];
+            }
+            uint16_t f[16];
+            mlp::features<T>(av, rv, pv, sqrt_eps, f);
+            lin = mlp::smooth_wave(s_mlp, scratch, f, logit_tau, lane);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            if (ROUTE && lin) linear5_pair<T>(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], pn[v], mn[v]);
+            else weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, pn[v], mn[v]);
+        }
         if (k >= z0 - 1) bad |= hllc<3, 2, T>(g, pk, mn, Fzn, Fzn[NV]);
 #pragma unroll
         for (int v = 0; v < NV; v++) pk[v] = pn[v];
-        if (k >= z0) {
+        if (k >= z0 && own) {
             const int64_t c = offset(g, gx, gy, k);
             T L[NV];
 #pragma unroll
@@ -242,18 +348,20 @@ __global__ void __launch_bounds__(kZX * kZY, 2)
     if (bad) atomicOr(flag, 1);
 }
 
-template <class T>
+template <class T, bool ROUTE>
 int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s)
 {
     const Grid &g = h->g;
     dim3 gxy((g.n[0] + TX - 1) / TX, (g.n[1] + TY - 1) / TY, (g.n[2] + kPlanesXY - 1) / kPlanesXY);
     dim3 gz((g.n[0] + kZX - 1) / kZX, (g.n[1] + kZY - 1) / kZY, (g.n[2] + kLZ - 1) / kLZ);
     T *lxy = (T *)h->lxy;
+    const T se = T(__builtin_sqrt(g.eps));
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_xy<T>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag);
+    hipLaunchKernelGGL((k_xy<T, ROUTE>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se);
     timing_end(h, s);
     timing_begin(h, s, 1);
-    hipLaunchKernelGGL((k_z<T>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag);
+    hipLaunchKernelGGL((k_z<T, ROUTE>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag, h->mlp,
+                       h->logit_tau, se);
     timing_end(h, s, 1);
     return hip_status(hipGetLastError(), "split right-hand side launch");
 }
@@ -264,9 +372,15 @@ int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int 
                      const double *dt_dev, hipStream_t s)
 {
     if (h->g.ndim != 3) return fail(MFC_E_UNSUPPORTED, "the split path is 3D only");
+    const bool learned = h->desc.recon == MFC_RECON_LEARNED;
+    if (learned && !h->mlp) return fail(MFC_E_ARG, "MFC_RECON_LEARNED needs mfc_set_indicator first");
+    const float *fq = (const float *)q, *fq0 = (const float *)q0;
+    const double *dq = (const double *)q, *dq0 = (const double *)q0;
     if (h->desc.precision == MFC_FP32_MIXED)
-        return rhs_split<float>(h, (const float *)q, (const float *)q0, (float *)out, mode, dt, dt_dev, s);
-    return rhs_split<double>(h, (const double *)q, (const double *)q0, (double *)out, mode, dt, dt_dev, s);
+        return learned ? rhs_split<float, true>(h, fq, fq0, (float *)out, mode, dt, dt_dev, s)
+                       : rhs_split<float, false>(h, fq, fq0, (float *)out, mode, dt, dt_dev, s);
+    return learned ? rhs_split<double, true>(h, dq, dq0, (double *)out, mode, dt, dt_dev, s)
+                   : rhs_split<double, false>(h, dq, dq0, (double *)out, mode, dt, dt_dev, s);
 }
 
 }  // namespace mfc

@@ -66,6 +66,16 @@ _SIGNATURES = {
     "mfc_check": [_VP, _VP],
     "mfc_set_kernel_timing": [_VP, ctypes.c_int],
     "mfc_kernel_time": [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "mfc_set_indicator": [_VP, ctypes.POINTER(ctypes.c_float), ctypes.c_double],
+    "mfc_harvest": [_VP, _VP, _VP, _VP, _VP, _VP],
+    "mfc_trainer_init": [ctypes.c_int64, ctypes.POINTER(_VP)],
+    "mfc_trainer_free": [_VP],
+    "mfc_trainer_set_params": [_VP, ctypes.POINTER(ctypes.c_float)],
+    "mfc_trainer_get_params": [_VP, ctypes.POINTER(ctypes.c_float)],
+    "mfc_trainer_grad": [_VP, _VP, _VP, _VP, ctypes.c_int64, _VP],
+    "mfc_trainer_read_grad": [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _VP],
+    "mfc_trainer_adam": [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP],
+    "mfc_trainer_infer": [_VP, _VP, ctypes.c_int64, _VP, _VP],
     "mfc_batch_init": [ctypes.POINTER(mfc_grid_desc), ctypes.c_int, ctypes.POINTER(_VP)],
     "mfc_batch_free": [_VP],
     "mfc_batch_layout": [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -290,6 +300,100 @@ class Solver:
 
     def check(self):
         mfc_check(self.h)
+
+    def set_indicator(self, params, tau):
+        mfc_set_indicator(self.h, params, tau)
+
+    def harvest(self, q):
+        """(features [ndim*cells, 16] int16 bf16 bits, labels uint8, max deviation float64), on the device."""
+        import torch
+        n = self.spec.cells * self.spec.ndim
+        X = torch.empty((n, 16), dtype=torch.int16, device="cuda")
+        Y = torch.empty(n, dtype=torch.uint8, device="cuda")
+        D = torch.empty(n, dtype=torch.float64, device="cuda")
+        mfc_harvest(self.h, q, X, Y, D)
+        return X, Y, D
+
+
+# ---------------------------------------------------------------------------
+# Learned indicator
+# ---------------------------------------------------------------------------
+
+NPARAM = 1601
+
+
+def _fptr(a):
+    import numpy as np
+    assert a.dtype == np.float32 and a.flags["C_CONTIGUOUS"] and a.size == NPARAM
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def mfc_set_indicator(h, params, tau: float):
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().mfc_set_indicator(h, _fptr(p), tau), "mfc_set_indicator")
+
+
+def mfc_harvest(h, q, features, labels, maxdev=None, stream=None):
+    _check(lib().mfc_harvest(h, _ptr(q), _ptr(features), _ptr(labels), _ptr(maxdev) if maxdev is not None else None,
+                             _stream(stream)), "mfc_harvest")
+
+
+class Trainer:
+    """FP32 master weights + Adam on the device; gradients from the library's
+    bf16 matrix-core kernels."""
+
+    def __init__(self, max_batch: int):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible; the library runs on the GPU only")
+        self.t = _VP()
+        _check(lib().mfc_trainer_init(max_batch, ctypes.byref(self.t)), "mfc_trainer_init")
+        self.max_batch = max_batch
+
+    def close(self):
+        if self.t:
+            _check(lib().mfc_trainer_free(self.t), "mfc_trainer_free")
+            self.t = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        import numpy as np
+        p = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().mfc_trainer_set_params(self.t, _fptr(p)), "mfc_trainer_set_params")
+
+    def params(self):
+        import numpy as np
+        p = np.empty(NPARAM, dtype=np.float32)
+        _check(lib().mfc_trainer_get_params(self.t, _fptr(p)), "mfc_trainer_get_params")
+        return p
+
+    def grad(self, X, Y, index=None, batch=None):
+        batch = (index.numel() if index is not None else X.shape[0]) if batch is None else batch
+        _check(lib().mfc_trainer_grad(self.t, _ptr(X), _ptr(Y), _ptr(index) if index is not None else None, batch,
+                                      _stream(None)), "mfc_trainer_grad")
+
+    def read_grad(self):
+        import numpy as np
+        g = np.empty(NPARAM, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(lib().mfc_trainer_read_grad(self.t, _fptr(g), ctypes.byref(loss), _stream(None)),
+               "mfc_trainer_read_grad")
+        return g, loss.value
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().mfc_trainer_adam(self.t, lr, beta1, beta2, eps, _stream(None)), "mfc_trainer_adam")
+
+    def infer(self, X):
+        import torch
+        prob = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().mfc_trainer_infer(self.t, _ptr(X), X.shape[0], _ptr(prob), _stream(None)), "mfc_trainer_infer")
+        return prob
 
 
 # ---------------------------------------------------------------------------

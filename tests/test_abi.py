@@ -127,3 +127,22 @@ def test_batch_null_arguments(L):
     assert L.mfc_batch_check(None, None) == mfc.MFC_E_ARG
     assert L.mfc_batch_time(None, None, None) == mfc.MFC_E_ARG
     assert L.mfc_batch_free(None) == mfc.MFC_OK
+
+
+def test_learned_null_arguments(L):
+    assert L.mfc_set_indicator(None, None, 0.5) == mfc.MFC_E_ARG
+    assert L.mfc_harvest(None, None, None, None, None, None) == mfc.MFC_E_ARG
+    assert L.mfc_trainer_init(0, ctypes.byref(ctypes.c_void_p())) == mfc.MFC_E_ARG
+    assert L.mfc_trainer_init(16, None) == mfc.MFC_E_ARG
+    assert L.mfc_trainer_grad(None, None, None, None, 1, None) == mfc.MFC_E_ARG
+    assert L.mfc_trainer_read_grad(None, None, None, None) == mfc.MFC_E_ARG
+    assert L.mfc_trainer_adam(None, 1e-3, 0.9, 0.999, 1e-8, None) == mfc.MFC_E_ARG
+    assert L.mfc_trainer_infer(None, None, 1, None, None) == mfc.MFC_E_ARG
+    assert L.mfc_trainer_set_params(None, None) == mfc.MFC_E_ARG
+    assert L.mfc_trainer_free(None) == mfc.MFC_OK
+
+
+def test_learned_recon_rejected_for_staged(L):
+    h = ctypes.c_void_p(123)
+    d = desc(recon=mfc.MFC_RECON_LEARNED)      # desc() builds a staged-kernel descriptor
+    assert L.mfc_init_grid(ctypes.byref(d), ctypes.byref(h)) == mfc.MFC_E_UNSUPPORTED
