@@ -202,7 +202,8 @@ def main():
                     help="bubble: the 3D bubble collapse (default); ensemble: 64 uneven 2D droplet-shock runs")
     ap.add_argument("--recon", choices=["weno5", "learned"], default="weno5",
                     help="learned: reconstruction routed by the trained indicator (weights from --weights)")
-    ap.add_argument("--tau", type=float, default=0.5, help="routing threshold on P(smooth)")
+    ap.add_argument("--tau", type=float, default=None,
+                    help="routing threshold on P(smooth) (default: the one stored beside the weights, else 0.5)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2305_09163_amd", "indicator_weights.npy"))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, scale-copy MIB MiB of float64 three times (a kernel of known HBM "
@@ -233,6 +234,9 @@ def main():
             sys.exit(f"bench.py: {args.weights} not found; train it with "
                      "`python -m paper_2305_09163_amd.train_indicator`")
         weights = np.load(args.weights, allow_pickle=False)
+        if args.tau is None:
+            meta = os.path.splitext(args.weights)[0] + ".json"
+            args.tau = json.load(open(meta))["tau"] if os.path.exists(meta) else 0.5
 
     def make_solver():
         s = mfc.Solver(spec, kernel=kernel, precision=precision,

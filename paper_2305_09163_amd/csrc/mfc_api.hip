@@ -54,15 +54,21 @@ constexpr int kThreads = 256;
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 // ------------------------------------------------------------ ghost fill
-// One thread per (variable, ghost layer, side, face-slab cell) of dimension d.
+// One thread per (variable, ghost layer, side, face-slab cell) of every
+// active dimension: the slabs of dimension d take the thread range
+// [start[d], start[d + 1]).
 template <class T>
-__global__ void __launch_bounds__(kThreads) k_ghosts(Grid g, T *__restrict__ q, int nv, int d, int bc_lo, int bc_hi)
+__global__ void __launch_bounds__(kThreads) k_ghosts(Grid g, T *__restrict__ q, int nv, int64_t s1, int64_t s2,
+                                                     int64_t s3)
 {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s3) return;
+    const int d = t < s1 ? 0 : (t < s2 ? 1 : 2);
+    t -= d == 0 ? 0 : (d == 1 ? s1 : s2);
+    const int bc_lo = g.bc[2 * d], bc_hi = g.bc[2 * d + 1];
     int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
     int n1 = g.n[o1], n2 = g.n[o2], n = g.n[d];
     int64_t per_var = (int64_t)2 * NG * n1 * n2;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= per_var * nv) return;
     int v = (int)(t / per_var);
     int64_t r = t % per_var;
     int a = (int)(r % n1);
@@ -262,12 +268,13 @@ template <class T>
 void fill_ghosts_t(mfc_grid *h, T *q, hipStream_t s)
 {
     const Grid &g = h->g;
-    for (int d = 0; d < g.ndim; d++) {
+    int64_t start[4] = {0, 0, 0, 0};
+    for (int d = 0; d < 3; d++) {
         int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
-        int64_t count = (int64_t)2 * NG * g.n[o1] * g.n[o2] * h->nvar;
-        hipLaunchKernelGGL((k_ghosts<T>), dim3(blocks_for(count)), dim3(kThreads), 0, s, g, q, h->nvar, d,
-                           h->desc.bc[2 * d], h->desc.bc[2 * d + 1]);
+        start[d + 1] = start[d] + (d < g.ndim ? (int64_t)2 * NG * g.n[o1] * g.n[o2] * h->nvar : 0);
     }
+    hipLaunchKernelGGL((k_ghosts<T>), dim3(blocks_for(start[3])), dim3(kThreads), 0, s, g, q, h->nvar, start[1],
+                       start[2], start[3]);
 }
 
 int fill_ghosts(mfc_grid *h, void *q, hipStream_t s)
@@ -367,6 +374,7 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
     g.h1 = desc->gamma[0] * desc->pi_inf[0] / (desc->gamma[0] - 1.0);
     g.h2 = desc->gamma[1] * desc->pi_inf[1] / (desc->gamma[1] - 1.0);
     g.eps = desc->weno_eps;
+    for (int f = 0; f < 6; f++) g.bc[f] = h->desc.bc[f];
     h->cells_padded = g.vstride;
     h->cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
     if (hipGetDevice(&h->device) != hipSuccess ||

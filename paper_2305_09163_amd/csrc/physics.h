@@ -35,6 +35,7 @@ struct Grid {
     // mixture EOS coefficients: Gamma = a1*g1 + (1-a1)*g2, Pi = a1*h1 + (1-a1)*h2
     double g1, g2, h1, h2;
     double eps;       // WENO epsilon
+    int bc[6];        // boundary kind per face (x-, x+, y-, y+, z-, z+): MFC_BC_*
 };
 
 // ---------------------------------------------------------------- reciprocal

@@ -30,14 +30,30 @@
 namespace mfc {
 namespace {
 
-constexpr int TX = 16, TY = 16, NT = TX * TY;
+// k_xy tile (cells) and workgroup (threads).  The thread count is fixed at
+// 256 and may exceed the tile, so that every phase takes a single pass: a
+// 16 x 14 tile needs 252 x- and 256 y-reconstructions and 238 / 240 faces,
+// where a 16 x 16 tile needs 288 and 272, i.e. a second, nearly empty pass
+// of one wavefront while the other three wait at the barrier.  Four planes
+// per workgroup (more workgroups) measured faster than 8 or 16.
+#ifndef MFC_XY_TX
+#define MFC_XY_TX 16
+#endif
+#ifndef MFC_XY_TY
+#define MFC_XY_TY 14
+#endif
+#ifndef MFC_XY_PLANES
+#define MFC_XY_PLANES 4
+#endif
+constexpr int TX = MFC_XY_TX, TY = MFC_XY_TY, NT = 256, NOWN = TX * TY;
+static_assert(NOWN <= NT, "one thread per tile cell");
 constexpr int PX = TX + 2 * NG, PY = TY + 2 * NG;
 constexpr int NPX = (TX + 2) * TY, NFX = (TX + 1) * TY;
 constexpr int NPY = TX * (TY + 2), NFY = TX * (TY + 1);
 constexpr int NP = NPX > NPY ? NPX : NPY;
 constexpr int NF = NFX > NFY ? NFX : NFY;
 constexpr int NHALO = 2 * NG * (TX + TY);
-constexpr int kPlanesXY = 8;    // planes per k_xy workgroup
+constexpr int kPlanesXY = MFC_XY_PLANES;  // planes per k_xy workgroup
 constexpr int kZX = 64, kZY = 4;  // k_z workgroup: 64 x 4 columns
 constexpr int kLZ = 16;          // planes per k_z workgroup
 
@@ -97,35 +113,63 @@ __global__ void __launch_bounds__(NT, 2)
     const int z0 = blockIdx.z * kPlanesXY, z1 = min(z0 + kPlanesXY, g.n[2]);
     const int xmax = g.n[0] + NG - 1, ymax = g.n[1] + NG - 1;
     const int gx = x0 + tx, gy = y0 + ty;
-    const bool own = gx < g.n[0] && gy < g.n[1];
+    const bool cell = tid < NOWN;                       // this thread has a tile cell
+    const bool own = cell && gx < g.n[0] && gy < g.n[1];
     bool bad = false;
+    // Each thread loads the conservative values of its own cell and of at
+    // most one halo cell of the next plane while the current plane is being
+    // processed, so the HBM latency of a plane overlaps a plane of work.
+    static_assert(NHALO <= NT, "one halo cell per thread");
+    const bool halo = tid < NHALO;
+    int hli = 0, hlj = 0;
+    if (tid < 2 * NG * TY) {
+        const int c = tid % (2 * NG), row = tid / (2 * NG);
+        hli = c < NG ? c : TX + c;
+        hlj = row + NG;
+    } else {
+        const int h2 = tid - 2 * NG * TY;
+        const int c = h2 % TX, r = h2 / TX;
+        hli = c + NG;
+        hlj = r < NG ? r : TY + r;
+    }
+    const int ox = min(gx, xmax), oy = min(gy, ymax);
+    const int hx = min(x0 + hli - NG, xmax), hy = min(y0 + hlj - NG, ymax);
+    T qo[NV], qh[NV];
+    auto fetch = [&](int k) {
+        if (cell) {
+            const int64_t c = offset(g, ox, oy, k);
+#pragma unroll
+            for (int v = 0; v < NV; v++) qo[v] = q[v * g.vstride + c];
+        }
+        if (halo) {
+            const int64_t c = offset(g, hx, hy, k);
+#pragma unroll
+            for (int v = 0; v < NV; v++) qh[v] = q[v * g.vstride + c];
+        }
+    };
+    fetch(z0);
 
     for (int k = z0; k < z1; k++) {
         // ---- plane k (own cell + x/y halos) into LDS as primitives
         {
-            T w[NV];
-            bad |= load_prim3<T>(g, q, min(gx, xmax), min(gy, ymax), k, w);
+            const int kout = k < 0 || k >= g.n[2];
+            if (cell) {
+                T w[NV];
+                const int outside = (ox < 0 || ox >= g.n[0]) + (oy < 0 || oy >= g.n[1]) + kout;
+                bad |= cons_to_prim<3, T>(g, qo, w) && outside <= 1;
 #pragma unroll
-            for (int v = 0; v < NV; v++) s_plane[v][ty + NG][tx + NG] = w[v];
-        }
-        for (int h = tid; h < NHALO; h += NT) {
-            int li, lj;
-            if (h < 2 * NG * TY) {
-                const int c = h % (2 * NG), row = h / (2 * NG);
-                li = c < NG ? c : TX + c;
-                lj = row + NG;
-            } else {
-                const int h2 = h - 2 * NG * TY;
-                const int c = h2 % TX, r = h2 / TX;
-                li = c + NG;
-                lj = r < NG ? r : TY + r;
+                for (int v = 0; v < NV; v++) s_plane[v][ty + NG][tx + NG] = w[v];
             }
-            T w[NV];
-            bad |= load_prim3<T>(g, q, min(x0 + li - NG, xmax), min(y0 + lj - NG, ymax), k, w);
+            if (halo) {
+                T w[NV];
+                const int outside = (hx < 0 || hx >= g.n[0]) + (hy < 0 || hy >= g.n[1]) + kout;
+                bad |= cons_to_prim<3, T>(g, qh, w) && outside <= 1;
 #pragma unroll
-            for (int v = 0; v < NV; v++) s_plane[v][lj][li] = w[v];
+                for (int v = 0; v < NV; v++) s_plane[v][hlj][hli] = w[v];
+            }
         }
         __syncthreads();
+        if (k + 1 < z1) fetch(k + 1);
 
         // ---- x: reconstruct cells -1 .. TX of every row, then the faces
         if constexpr (ROUTE) {
@@ -177,7 +221,7 @@ __global__ void __launch_bounds__(NT, 2)
         __syncthreads();
         const T idx = T(g.inv_dx[0]), idy = T(g.inv_dx[1]);
         T L[NV], divu;
-        {
+        if (cell) {
             const int f = ty * (TX + 1) + tx;
 #pragma unroll
             for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * idx;
@@ -237,7 +281,7 @@ __global__ void __launch_bounds__(NT, 2)
             s_flux[NV][f] = uf;
         }
         __syncthreads();
-        {
+        if (cell) {
             const int f = ty * TX + tx;
 #pragma unroll
             for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * idy;

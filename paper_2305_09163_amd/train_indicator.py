@@ -7,11 +7,14 @@ orders the calls and draws the (seeded) sample indices.
     python -m paper_2305_09163_amd.train_indicator [--samples 1e7] [--steps N] [--out FILE]
 
 writes the 1601 FP32 parameters (flat order of include/mfc.h) to FILE
-(default: indicator_weights.npy next to this module).
+(default: indicator_weights.npy next to this module) and, beside it, a .json
+with the routing threshold chosen on held-out samples (the smallest tau
+whose false-smooth rate is at most 1e-3) and the training record.
 """
 from __future__ import annotations
 
 import argparse
+import json
 import math
 import os
 import sys
@@ -60,10 +63,11 @@ def harvest_runs(runs, log=print):
     return torch.cat(Xs), torch.cat(Ys)
 
 
-def train(X, Y, steps: int, batch: int = 8192, lr: float = 3e-3, seed: int = 0, params=None, log=print,
-          log_every: int = 500):
-    """Adam on mean BCE; batches drawn uniformly with replacement (seeded).
-    Returns the trained FP32 parameters and the loss history."""
+def train(X, Y, steps: int, batch: int = 4096, lr: float = 3e-3, seed: int = 0, params=None, log=print,
+          log_every: int = 500, balanced: bool = True):
+    """Adam on mean BCE; batches drawn with replacement (seeded), half from
+    each label when `balanced` (the classes are far from even on these
+    workloads).  Returns the trained FP32 parameters and the loss history."""
     import torch
 
     from . import mfc
@@ -73,9 +77,17 @@ def train(X, Y, steps: int, batch: int = 8192, lr: float = 3e-3, seed: int = 0, 
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
     n = int(Y.numel())
+    pos = torch.nonzero(Y == 1).reshape(-1).to(torch.int32)
+    neg = torch.nonzero(Y == 0).reshape(-1).to(torch.int32)
+    balanced = balanced and len(pos) > 0 and len(neg) > 0
     hist = []
     for k in range(steps):
-        idx = torch.randint(0, n, (batch,), generator=gen, device="cuda", dtype=torch.int32)
+        if balanced:
+            h = batch // 2
+            idx = torch.cat([pos[torch.randint(0, len(pos), (h,), generator=gen, device="cuda")],
+                             neg[torch.randint(0, len(neg), (batch - h,), generator=gen, device="cuda")]])
+        else:
+            idx = torch.randint(0, n, (batch,), generator=gen, device="cuda", dtype=torch.int32)
         t.grad(X, Y, idx)
         if k % log_every == 0 or k == steps - 1:
             _, loss = t.read_grad()
@@ -105,6 +117,24 @@ def evaluate(params, X, Y, tau: float = 0.5):
             "labelled_smooth": float(y.float().mean())}
 
 
+def choose_tau(params, X, Y, max_false_smooth: float = 1e-3):
+    """The smallest threshold whose false-smooth rate (non-smooth samples
+    routed to the linear stencil) on (X, Y) is at most max_false_smooth."""
+    from . import mfc
+
+    t = mfc.Trainer(1)
+    t.set_params(params)
+    P = t.infer(X)
+    t.close()
+    Pn = P[Y == 0]
+    if Pn.numel() == 0:
+        return 0.5
+    # the (1 - max_false_smooth) quantile of the non-smooth samples' outputs
+    k = int(Pn.numel() * (1.0 - max_false_smooth))
+    tau = float(Pn.sort().values[min(k, Pn.numel() - 1)])
+    return min(max(tau, 0.5), 0.999999)
+
+
 def default_runs(n3: int = 128):
     from . import workloads as W
 
@@ -118,7 +148,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--samples", type=float, default=1e7, help="training samples kept (drawn without replacement)")
     ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--n3", type=int, default=128, help="bubble grid size")
     ap.add_argument("--seed", type=int, default=230509163)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
@@ -136,11 +167,20 @@ def main(argv=None):
     keep = keep[:-100000]
     Xt, Yt = X[keep].contiguous(), Y[keep].contiguous()
     log(f"training set: {int(Yt.numel())} samples, {float(Yt.float().mean()):.3f} labelled smooth")
-    params, _ = train(Xt, Yt, args.steps, args.batch, seed=args.seed % 1000, log=log)
-    for tau in (0.5, 0.9):
-        log(f"held-out, tau {tau}: {evaluate(params, X[held].contiguous(), Y[held].contiguous(), tau)}")
+    params, hist = train(Xt, Yt, args.steps, args.batch, lr=args.lr, seed=args.seed % 1000, log=log)
+    Xh, Yh = X[held].contiguous(), Y[held].contiguous()
+    tau = choose_tau(params, Xh, Yh)
+    stats = {t: evaluate(params, Xh, Yh, t) for t in (0.5, tau)}
+    for t, ev in stats.items():
+        log(f"held-out, tau {t:.6f}: {ev}")
     np.save(args.out, params.astype(np.float32), allow_pickle=False)
-    log(f"wrote {args.out}")
+    meta = {"tau": tau, "rule": "false-smooth rate <= 1e-3 on 100k held-out samples (floor 0.5)",
+            "held_out": {str(t): ev for t, ev in stats.items()}, "samples": int(Yt.numel()),
+            "labelled_smooth": float(Yt.float().mean()), "steps": args.steps, "batch": args.batch,
+            "lr": args.lr, "balanced": True, "loss": hist, "bubble_n": args.n3}
+    with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
+        json.dump(meta, f, indent=1)
+    log(f"wrote {args.out} (tau {tau:.6f})")
     return 0
 
 

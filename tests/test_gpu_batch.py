@@ -27,6 +27,12 @@ def ensemble(sizes, seed0=100):
     return [W.droplet_shock_2d(n, W.SEED + seed0 + i) for i, n in enumerate(sizes)]
 
 
+def interior(q):
+    """Interior cells of a 2D state [v, 1, py, px] (ghost cells after a step
+    hold whatever the last fill left: not part of the result)."""
+    return q[:, :, 3:-3, 3:-3]
+
+
 def single_runs(runs, prec, nsteps, cfl=0.3):
     out = []
     for spec, w in runs:
@@ -49,7 +55,7 @@ def test_batch_matches_single_grid_runs_bitwise(prec):
     b.check()
     times = b.time()
     for r, ((q1, t1), q, t) in enumerate(zip(single_runs(runs, prec, 10), qs, times)):
-        assert torch.equal(q, q1), f"run {r} differs from the single-grid path"
+        assert torch.equal(interior(q), interior(q1)), f"run {r} differs from the single-grid path"
         assert t == t1 and t > 0.0, (r, t, t1)
 
 
@@ -169,5 +175,5 @@ def test_full_ensemble_sampled_runs_match_single_grid():
     order = np.argsort(sizes)
     for r in (int(order[0]), int(order[-1]), int(order[32])):
         (q1, t1), = single_runs([runs[r]], "fp32", 5)
-        assert torch.equal(qs[r], q1), r
+        assert torch.equal(interior(qs[r]), interior(q1)), r
         assert b.time()[r] == t1
