@@ -29,6 +29,7 @@ struct mfc_grid {
     double *faces = nullptr;   // staged path: 3 directions x (nvar + 1) face arrays
     double *lxy = nullptr;     // split path: x+y flux differences and div(u), nvar + 1 arrays
     double *partial = nullptr; // per-block maxima of the wave-speed reduction
+    int64_t partial_len = 0;   // its length (the larger of the two producers' grids)
     double *scalars = nullptr; // [0] smax, [1] dt, [2] t, [3] spare
     int *flag = nullptr;       // non-physical flag
     float *mlp = nullptr;      // learned indicator parameters (FP32, flat order of mlp.h)
@@ -62,6 +63,14 @@ int launch_rhs_staged(mfc_grid *h, const void *q, const void *q0, void *out, int
 int launch_rhs_fused(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
                      const double *dt_dev, hipStream_t s);
 int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
-                     const double *dt_dev, hipStream_t s);
+                     const double *dt_dev, hipStream_t s, double cfl = 0.0);
+
+// Split path: number of x+y workgroups of one launch (each writes one
+// wave-speed partial when the step size is computed inside the launch).
+int64_t split_xy_blocks(const Grid &g);
+
+// Reduce nblocks partial maxima, set the step size (cfl > 0: from the
+// maxima; else dt) and advance the accumulated time, on the device.
+void launch_step_begin(mfc_grid *h, const double *partial, int nblocks, double cfl, double dt, hipStream_t s);
 
 }  // namespace mfc

@@ -71,12 +71,26 @@ __global__ void __launch_bounds__(kThreads) k_ghosts(Grid g, T *__restrict__ q, 
     int64_t per_var = (int64_t)2 * NG * n1 * n2;
     int v = (int)(t / per_var);
     int64_t r = t % per_var;
-    int a = (int)(r % n1);
-    r /= n1;
-    int b = (int)(r % n2);
-    r /= n2;
-    int l = 1 + (int)(r % NG);
-    int side = (int)(r / NG);
+    int a, b, l, side;
+    if (d == 0) {
+        // x slabs are 3 cells wide: let consecutive threads take the
+        // consecutive ghost cells of a row (x = -3, -2, -1 and n .. n+2)
+        const int u = (int)(r % NG);
+        r /= NG;
+        side = (int)(r % 2);
+        r /= 2;
+        a = (int)(r % n1);
+        b = (int)(r / n1);
+        l = side == 0 ? NG - u : 1 + u;
+    } else {
+        // y and z slabs: consecutive threads take consecutive x
+        a = (int)(r % n1);
+        r /= n1;
+        b = (int)(r % n2);
+        r /= n2;
+        l = 1 + (int)(r % NG);
+        side = (int)(r / NG);
+    }
     int c[3], src[3];
     c[o1] = src[o1] = a;
     c[o2] = src[o2] = b;
@@ -277,6 +291,16 @@ void fill_ghosts_t(mfc_grid *h, T *q, hipStream_t s)
                        start[2], start[3]);
 }
 
+}  // namespace
+
+void launch_step_begin(mfc_grid *h, const double *partial, int nblocks, double cfl, double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(kReduceThreads), 0, s, partial, nblocks, cfl, dt, h->g.dxmin,
+                       h->scalars);
+}
+
+namespace {
+
 int fill_ghosts(mfc_grid *h, void *q, hipStream_t s)
 {
     if (is_fp32(h)) fill_ghosts_t<float>(h, (float *)q, s);
@@ -399,7 +423,8 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
     }
     if (desc->kernel == MFC_KERNEL_SPLIT)
         alloc((void **)&h->lxy, (int64_t)(h->nvar + 1) * h->cells_padded * elem_bytes(h));
-    alloc((void **)&h->partial, kReduceBlocks * 8);
+    h->partial_len = std::max<int64_t>(kReduceBlocks, desc->ndim == 3 ? split_xy_blocks(g) : 0);
+    alloc((void **)&h->partial, h->partial_len * 8);
     alloc((void **)&h->scalars, 4 * 8);
     alloc((void **)&h->flag, 8);
     if (e != hipSuccess) {
@@ -522,15 +547,19 @@ int mfc_rk3_step(mfc_grid *h, void *qv, double cfl, double dt, void *stream)
     void *q = qv, *A = h->stage_a, *B = h->stage_b;
     const double *dt_dev = h->scalars + 1;
     if ((st = fill_ghosts(h, q, s))) return st;
-    if (cfl > 0.0) {
-        if ((st = wavespeed(h, q, s))) return st;
-        hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(kReduceThreads), 0, s, h->partial, kReduceBlocks, cfl, 0.0,
-                           h->g.dxmin, h->scalars);
+    if (h->desc.kernel == MFC_KERNEL_SPLIT && cfl > 0.0) {
+        // the x+y pass of the first stage reduces the wave speeds of q^n and
+        // the step size is set before its z pass, the first to use it
+        if ((st = launch_rhs_split(h, q, q, A, 1, 0.0, dt_dev, s, cfl))) return st;
     } else {
-        hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(kReduceThreads), 0, s, nullptr, 0, 0.0, dt, h->g.dxmin,
-                           h->scalars);
+        if (cfl > 0.0) {
+            if ((st = wavespeed(h, q, s))) return st;
+            launch_step_begin(h, h->partial, kReduceBlocks, cfl, 0.0, s);
+        } else {
+            launch_step_begin(h, nullptr, 0, 0.0, dt, s);
+        }
+        if ((st = rhs_dispatch(h, q, q, A, 1, 0.0, dt_dev, s))) return st;
     }
-    if ((st = rhs_dispatch(h, q, q, A, 1, 0.0, dt_dev, s))) return st;
     if ((st = fill_ghosts(h, A, s))) return st;
     if ((st = rhs_dispatch(h, A, q, B, 2, 0.0, dt_dev, s))) return st;
     if ((st = fill_ghosts(h, B, s))) return st;

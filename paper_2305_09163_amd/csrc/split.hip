@@ -55,7 +55,15 @@ constexpr int NF = NFX > NFY ? NFX : NFY;
 constexpr int NHALO = 2 * NG * (TX + TY);
 constexpr int kPlanesXY = MFC_XY_PLANES;  // planes per k_xy workgroup
 constexpr int kZX = 64, kZY = 4;  // k_z workgroup: 64 x 4 columns
-constexpr int kLZ = 16;          // planes per k_z workgroup
+#ifndef MFC_Z_LZ64
+#define MFC_Z_LZ64 16
+#endif
+#ifndef MFC_Z_LZ32
+#define MFC_Z_LZ32 16
+#endif
+// planes per k_z column chunk (the march re-reads 6 halo planes per chunk)
+template <class T>
+constexpr int kLZ = sizeof(T) == 8 ? MFC_Z_LZ64 : MFC_Z_LZ32;
 
 __device__ __forceinline__ int64_t offset(const Grid &g, int i, int j, int k)
 {
@@ -90,10 +98,15 @@ struct RouteLds {
     static constexpr int own_words = (ROUTE && !in_flux) ? kFeatWords : 1;
 };
 
+// When smax_partial is not null (first stage of a step with a CFL step size)
+// the kernel also reduces max_d (|u_d| + c) over its interior cells, the
+// quantity of the CFL condition (Sec. 1), and writes one maximum per
+// workgroup: the step size is then set between this launch and the z pass,
+// which is the first to use it.
 template <class T, bool ROUTE>
 __global__ void __launch_bounds__(NT, 2)
     k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag,
-         const float *__restrict__ mlpw, float logit_tau, T sqrt_eps)
+         const float *__restrict__ mlpw, float logit_tau, T sqrt_eps, double *__restrict__ smax_partial)
 {
     constexpr int NV = 7;
     using R = RouteLds<T, ROUTE>;
@@ -116,6 +129,7 @@ __global__ void __launch_bounds__(NT, 2)
     const bool cell = tid < NOWN;                       // this thread has a tile cell
     const bool own = cell && gx < g.n[0] && gy < g.n[1];
     bool bad = false;
+    double smax = 0.0;
     // Each thread loads the conservative values of its own cell and of at
     // most one halo cell of the next plane while the current plane is being
     // processed, so the HBM latency of a plane overlaps a plane of work.
@@ -159,6 +173,13 @@ __global__ void __launch_bounds__(NT, 2)
                 bad |= cons_to_prim<3, T>(g, qo, w) && outside <= 1;
 #pragma unroll
                 for (int v = 0; v < NV; v++) s_plane[v][ty + NG][tx + NG] = w[v];
+                if (smax_partial && own) {
+                    double Gam, Pi;
+                    mixture<double>(g, double(w[6]), Gam, Pi);
+                    const double cs = __builtin_sqrt(sound2<double>(Gam, Pi, double(w[0]) + double(w[1]), double(w[5])));
+#pragma unroll
+                    for (int d = 0; d < 3; d++) smax = __builtin_fmax(smax, __builtin_fabs(double(w[2 + d])) + cs);
+                }
             }
             if (halo) {
                 T w[NV];
@@ -296,6 +317,20 @@ __global__ void __launch_bounds__(NT, 2)
         // the next plane overwrites s_plane (last read before the y-face
         // barrier) and s_pair/s_flux only after two more barriers
     }
+    if (smax_partial) {
+        // workgroup maximum: wavefront butterflies, then one value per wavefront
+        __shared__ double s_red[NT / 64];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) smax = __builtin_fmax(smax, __shfl_xor(smax, o, 64));
+        if (lane == 0) s_red[tid / 64] = smax;
+        __syncthreads();
+        if (tid == 0) {
+            double m = s_red[0];
+#pragma unroll
+            for (int w = 1; w < NT / 64; w++) m = __builtin_fmax(m, s_red[w]);
+            smax_partial[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = m;
+        }
+    }
     if (bad) atomicOr(flag, 1);
 }
 
@@ -328,7 +363,7 @@ __global__ void __launch_bounds__(kZX * kZY, 2)
     }
     uint16_t *scratch = s_feat + (ROUTE ? (threadIdx.x / 64) * 64 * 16 : 0);
     const int lane = threadIdx.x % 64;
-    const int z0 = blockIdx.z * kLZ, z1 = min(z0 + kLZ, g.n[2]);
+    const int z0 = blockIdx.z * kLZ<T>, z1 = min(z0 + kLZ<T>, g.n[2]);
     const T hdt = T(mode ? (dt_dev ? *dt_dev : dt) : 0.0);
     const T ca = T(mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0));
     const T cb = T(mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0));
@@ -392,17 +427,25 @@ __global__ void __launch_bounds__(kZX * kZY, 2)
     if (bad) atomicOr(flag, 1);
 }
 
+dim3 xy_grid(const Grid &g)
+{
+    return dim3((g.n[0] + TX - 1) / TX, (g.n[1] + TY - 1) / TY, (g.n[2] + kPlanesXY - 1) / kPlanesXY);
+}
+
 template <class T, bool ROUTE>
-int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s)
+int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s,
+              double cfl)
 {
     const Grid &g = h->g;
-    dim3 gxy((g.n[0] + TX - 1) / TX, (g.n[1] + TY - 1) / TY, (g.n[2] + kPlanesXY - 1) / kPlanesXY);
-    dim3 gz((g.n[0] + kZX - 1) / kZX, (g.n[1] + kZY - 1) / kZY, (g.n[2] + kLZ - 1) / kLZ);
+    const dim3 gxy = xy_grid(g);
+    dim3 gz((g.n[0] + kZX - 1) / kZX, (g.n[1] + kZY - 1) / kZY, (g.n[2] + kLZ<T> - 1) / kLZ<T>);
     T *lxy = (T *)h->lxy;
     const T se = T(__builtin_sqrt(g.eps));
+    double *partial = cfl > 0.0 ? h->partial : nullptr;
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_xy<T, ROUTE>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se);
+    hipLaunchKernelGGL((k_xy<T, ROUTE>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se, partial);
     timing_end(h, s);
+    if (partial) launch_step_begin(h, partial, (int)split_xy_blocks(g), cfl, 0.0, s);
     timing_begin(h, s, 1);
     hipLaunchKernelGGL((k_z<T, ROUTE>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag, h->mlp,
                        h->logit_tau, se);
@@ -412,8 +455,14 @@ int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
 
 }  // namespace
 
+int64_t split_xy_blocks(const Grid &g)
+{
+    const dim3 b = xy_grid(g);
+    return (int64_t)b.x * b.y * b.z;
+}
+
 int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
-                     const double *dt_dev, hipStream_t s)
+                     const double *dt_dev, hipStream_t s, double cfl)
 {
     if (h->g.ndim != 3) return fail(MFC_E_UNSUPPORTED, "the split path is 3D only");
     const bool learned = h->desc.recon == MFC_RECON_LEARNED;
@@ -421,10 +470,10 @@ int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int 
     const float *fq = (const float *)q, *fq0 = (const float *)q0;
     const double *dq = (const double *)q, *dq0 = (const double *)q0;
     if (h->desc.precision == MFC_FP32_MIXED)
-        return learned ? rhs_split<float, true>(h, fq, fq0, (float *)out, mode, dt, dt_dev, s)
-                       : rhs_split<float, false>(h, fq, fq0, (float *)out, mode, dt, dt_dev, s);
-    return learned ? rhs_split<double, true>(h, dq, dq0, (double *)out, mode, dt, dt_dev, s)
-                   : rhs_split<double, false>(h, dq, dq0, (double *)out, mode, dt, dt_dev, s);
+        return learned ? rhs_split<float, true>(h, fq, fq0, (float *)out, mode, dt, dt_dev, s, cfl)
+                       : rhs_split<float, false>(h, fq, fq0, (float *)out, mode, dt, dt_dev, s, cfl);
+    return learned ? rhs_split<double, true>(h, dq, dq0, (double *)out, mode, dt, dt_dev, s, cfl)
+                   : rhs_split<double, false>(h, dq, dq0, (double *)out, mode, dt, dt_dev, s, cfl);
 }
 
 }  // namespace mfc
