@@ -314,6 +314,39 @@ def interface_advection(ndim: int, n: int, u: float = 100.0, p: float = 1.0e5, w
     return spec, _assemble(spec, alpha1 * np.ones(spec.shape[1:]), 1000.0, 1.2, vel, p)
 
 
+def uniform_state(ndim: int, n, alpha1: float = 0.4, vel=(37.0, -12.0, 5.0), p: float = 2.0e5):
+    """A uniform two-fluid state (extrapolation boundaries): its exact
+    right-hand side is zero."""
+    spec = GridSpec(ndim=ndim, n=(n,) * ndim if isinstance(n, int) else tuple(n))
+    return spec, _assemble(spec, alpha1, 1000.0, 1.2, list(vel[:ndim]), p)
+
+
+def supersonic_periodic(ndim: int, n: int, mach: float = 2.5, sign: float = 1.0, seed_offset: int = 9):
+    """The smooth periodic state of random_smooth_periodic with both fluids
+    air-like ideal gases and a uniform velocity of `mach` times the largest
+    sound speed added along every direction (sign -1: towards -x, -y, -z),
+    so that every face is supersonic and the HLLC flux is one-sided."""
+    spec0, w = random_smooth_periodic(ndim, n, seed_offset=seed_offset)
+    spec = GridSpec(ndim=ndim, n=spec0.n[:ndim], bc=spec0.bc, **ideal_pair())
+    rho = w[0] + w[1]
+    p = w[2 + ndim]
+    cmax = float(np.sqrt(1.4 * p / rho).max())
+    for d in range(ndim):
+        w[2 + d] = w[2 + d] + sign * mach * cmax
+    return spec, w
+
+
+def sod_1d(n: int = 100):
+    """Sod's problem with both fluids the same ideal gas (gamma 1.4): rho, p =
+    (1, 1) for x < 0.5 and (0.125, 0.1) after, u = 0, alpha1 = 0.5."""
+    spec = GridSpec(ndim=1, n=(n,), **ideal_pair())
+    x, _, _ = spec.mesh()
+    left = x < 0.5
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    return spec, _assemble(spec, 0.5, rho, rho, [np.zeros_like(x)], p)
+
+
 def random_smooth_periodic(ndim: int, n: int, seed_offset: int = 7, modes: int = 3):
     """Random smooth periodic state (sums of low Fourier modes) with both
     fluids present everywhere: alpha1 in [0.3, 0.7], densities near water and
