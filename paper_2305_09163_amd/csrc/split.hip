@@ -1,16 +1,18 @@
 // Split right-hand side (3D): two launches per Runge-Kutta stage.
 //
 //   k_xy  x and y directions of eq. (fvmdis) (Sec. 3.1): a workgroup of
-//         16 x 16 threads owns a 16 x 16 tile of one plane; the plane (with
-//         3-cell halos) is converted to primitives into LDS once, every cell
-//         of the tile plus one halo cell per side is reconstructed once per
-//         direction (WENO5, both face values from one stencil, Sec. 3.2), the
-//         HLLC flux of every face (Sec. 3.2.1) is computed once and shared by
-//         the two cells of the face.  It writes the x+y flux differences and
-//         the x+y face-velocity divergence of every cell (8 values).
+//         256 threads owns a 16 x 13 tile of an x-y plane and walks four
+//         planes; each plane (with 3-cell halos) is converted to primitives
+//         into LDS once, every cell of the tile plus one halo cell per side is
+//         reconstructed once per direction (WENO5, both face values from one
+//         stencil, Sec. 3.2), the HLLC flux of every face (Sec. 3.2.1) is
+//         computed once and shared by the two cells of the face.  It writes
+//         the x+y flux differences and the x+y face-velocity divergence of
+//         every cell (8 values).
 //   k_z   z direction plus the stage update: one thread per (x, y) column
 //         marches through a chunk of planes with the primitives of five
-//         planes in registers, reconstructs each cell once (both faces) and
+//         planes at hand (four in a per-thread LDS ring, the newest in
+//         registers), reconstructs each cell once (both faces) and
 //         solves each z face once, adds the x+y part, forms the alpha1 div(u)
 //         source and the SSP-RK3 combination and writes the stage result.
 //
@@ -31,16 +33,18 @@ namespace mfc {
 namespace {
 
 // k_xy tile (cells) and workgroup (threads).  The thread count is fixed at
-// 256 and may exceed the tile, so that every phase takes a single pass: a
-// 16 x 14 tile needs 252 x- and 256 y-reconstructions and 238 / 240 faces,
-// where a 16 x 16 tile needs 288 and 272, i.e. a second, nearly empty pass
-// of one wavefront while the other three wait at the barrier.  Four planes
-// per workgroup (more workgroups) measured faster than 8 or 16.
+// 256 and may exceed the tile, so that every phase takes a single pass: one
+// thread per reconstruction and direction, the same thread then solving the
+// face on the reconstruction's + side with its own + value kept in
+// registers, so that only the - values pass through LDS.  With a 16 x 13 tile
+// the FP64 kernel's LDS (primitives, - values, face fluxes: 51.8 KB) admits
+// three workgroups per CU; 16 x 14 needs 54.8 KB and admits two.  Four
+// planes per workgroup (more workgroups) measured faster than 8 or 16.
 #ifndef MFC_XY_TX
 #define MFC_XY_TX 16
 #endif
 #ifndef MFC_XY_TY
-#define MFC_XY_TY 14
+#define MFC_XY_TY 13
 #endif
 #ifndef MFC_XY_PLANES
 #define MFC_XY_PLANES 4
@@ -48,13 +52,22 @@ namespace {
 constexpr int TX = MFC_XY_TX, TY = MFC_XY_TY, NT = 256, NOWN = TX * TY;
 static_assert(NOWN <= NT, "one thread per tile cell");
 constexpr int PX = TX + 2 * NG, PY = TY + 2 * NG;
-constexpr int NPX = (TX + 2) * TY, NFX = (TX + 1) * TY;
-constexpr int NPY = TX * (TY + 2), NFY = TX * (TY + 1);
+constexpr int NPX = (TX + 2) * TY;  // x reconstructions: cells -1 .. TX of every row
+constexpr int NPY = TX * (TY + 2);  // y reconstructions: rows -1 .. TY of every column
+static_assert(NPX <= NT && NPY <= NT, "one reconstruction per thread and direction");
 constexpr int NP = NPX > NPY ? NPX : NPY;
+// A face is indexed by the reconstruction on its low side: x face p lies
+// between reconstructions p and p + 1 of a row (p % (TX + 2) <= TX), y face p
+// between reconstructions p and p + TX (p / TX <= TY).
+constexpr int NFX = (TX + 2) * (TY - 1) + TX + 1;
+constexpr int NFY = TX * (TY + 1);
 constexpr int NF = NFX > NFY ? NFX : NFY;
 constexpr int NHALO = 2 * NG * (TX + TY);
 constexpr int kPlanesXY = MFC_XY_PLANES;  // planes per k_xy workgroup
-constexpr int kZX = 64, kZY = 4;  // k_z workgroup: 64 x 4 columns
+#ifndef MFC_Z_Y
+#define MFC_Z_Y 4
+#endif
+constexpr int kZX = 64, kZY = MFC_Z_Y;  // k_z workgroup: 64 x 4 columns
 #ifndef MFC_Z_LZ64
 #define MFC_Z_LZ64 16
 #endif
@@ -64,6 +77,28 @@ constexpr int kZX = 64, kZY = 4;  // k_z workgroup: 64 x 4 columns
 // planes per k_z column chunk (the march re-reads 6 halo planes per chunk)
 template <class T>
 constexpr int kLZ = sizeof(T) == 8 ? MFC_Z_LZ64 : MFC_Z_LZ32;
+
+#ifndef MFC_XCD
+#define MFC_XCD 1
+#endif
+
+// Logical tile of this workgroup.  Workgroup ids are handed to the eight XCDs
+// round-robin (id % 8), and each XCD has its own L2; renumbering the tiles so
+// that XCD j receives the j-th contiguous range of tiles (x fastest, then y,
+// then z) keeps tiles that read each other's halo cells in one L2.  The map
+// is a bijection for any grid size, so correctness never depends on it.
+__device__ __forceinline__ void tile_of_block(int &bx, int &by, int &bz)
+{
+    const int gxn = gridDim.x, gyn = gridDim.y;
+    int lin = blockIdx.x + gxn * (blockIdx.y + gyn * blockIdx.z);
+    if (MFC_XCD) {
+        const int n = gxn * gyn * gridDim.z, x = lin % 8, base = n / 8, extra = n % 8;
+        lin = x * base + min(x, extra) + lin / 8;
+    }
+    bx = lin % gxn;
+    by = (lin / gxn) % gyn;
+    bz = lin / (gxn * gyn);
+}
 
 __device__ __forceinline__ int64_t offset(const Grid &g, int i, int j, int k)
 {
@@ -104,15 +139,15 @@ struct RouteLds {
 // workgroup: the step size is then set between this launch and the z pass,
 // which is the first to use it.
 template <class T, bool ROUTE>
-__global__ void __launch_bounds__(NT, 2)
+__global__ void __launch_bounds__(NT, 3)
     k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag,
          const float *__restrict__ mlpw, float logit_tau, T sqrt_eps, double *__restrict__ smax_partial)
 {
     constexpr int NV = 7;
     using R = RouteLds<T, ROUTE>;
     __shared__ T s_plane[NV][PY][PX];
-    __shared__ T s_pair[2 * NV][NP];
-    __shared__ __align__(16) T s_flux[NV + 1][NF];
+    __shared__ T s_minus[NV][NP];                    // - face value of every reconstruction
+    __shared__ __align__(16) T s_flux[NV + 1][NF];   // flux and face velocity of every face
     __shared__ __align__(16) typename R::P s_mlp;
     __shared__ __align__(16) uint16_t s_feat_own[R::own_words];
     const T eps = T(g.eps);
@@ -122,8 +157,10 @@ __global__ void __launch_bounds__(NT, 2)
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int z0 = blockIdx.z * kPlanesXY, z1 = min(z0 + kPlanesXY, g.n[2]);
+    int bx, by, bz;
+    tile_of_block(bx, by, bz);
+    const int x0 = bx * TX, y0 = by * TY;
+    const int z0 = bz * kPlanesXY, z1 = min(z0 + kPlanesXY, g.n[2]);
     const int xmax = g.n[0] + NG - 1, ymax = g.n[1] + NG - 1;
     const int gx = x0 + tx, gy = y0 + ty;
     const bool cell = tid < NOWN;                       // this thread has a tile cell
@@ -192,114 +229,93 @@ __global__ void __launch_bounds__(NT, 2)
         __syncthreads();
         if (k + 1 < z1) fetch(k + 1);
 
-        // ---- x: reconstruct cells -1 .. TX of every row, then the faces
-        if constexpr (ROUTE) {
-            for (int p0 = 0; p0 < NPX; p0 += NT) {  // uniform trip count: whole wavefronts classify
-                const int p = p0 + tid;
-                const bool valid = p < NPX;
-                const int pc = valid ? p : NPX - 1;
-                const int row = pc / (TX + 2), c = pc % (TX + 2);
-                bool lin = false;
+        // ---- x: thread p reconstructs cell p % (TX + 2) - 1 of row p / (TX + 2)
+        // and solves the face on its + side
+        T wP[NV];  // + face values of this thread's reconstruction
+        {
+            const int p = tid;
+            const bool valid = p < NPX;
+            const int pc = valid ? p : NPX - 1;
+            const int row = pc / (TX + 2), c = pc % (TX + 2);
+            bool lin = false;
+            if constexpr (ROUTE) {  // whole wavefronts classify together
                 if (__ballot(valid))
                     lin = mlp::smooth_stencil<T>(s_mlp, scratch, &s_plane[6][row + NG][c], &s_plane[0][row + NG][c],
                                                  &s_plane[1][row + NG][c], &s_plane[5][row + NG][c], 1, sqrt_eps,
                                                  logit_tau, lane);
-                if (valid) {
-#pragma unroll
-                    for (int v = 0; v < NV; v++) {
-                        const T *s = &s_plane[v][row + NG][c];
-                        if (lin) linear5_pair<T>(s[0], s[1], s[2], s[3], s[4], s_pair[v][p], s_pair[NV + v][p]);
-                        else weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
-                    }
-                }
             }
-        } else {
-            for (int p = tid; p < NPX; p += NT) {
-                const int row = p / (TX + 2), c = p % (TX + 2);
+            if (valid) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
-                    const T *s = &s_plane[v][row + NG][c];
-                    weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                    const T *st = &s_plane[v][row + NG][c];
+                    if (ROUTE && lin) linear5_pair<T>(st[0], st[1], st[2], st[3], st[4], wP[v], s_minus[v][p]);
+                    else weno5_pair(st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
                 }
             }
         }
         __syncthreads();
-        for (int f = tid; f < NFX; f += NT) {
-            const int row = f / (TX + 1), fi = f % (TX + 1);
-            const int pl = row * (TX + 2) + fi;
-            T wL[NV], wR[NV], F[NV], uf;
+        {
+            const int p = tid, row = p / (TX + 2), c = p % (TX + 2);
+            if (p < NPX && c <= TX) {
+                T wR[NV], F[NV], uf;
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                wL[v] = s_pair[v][pl];
-                wR[v] = s_pair[NV + v][pl + 1];
+                for (int v = 0; v < NV; v++) wR[v] = s_minus[v][p + 1];
+                const bool b = hllc<3, 0, T>(g, wP, wR, F, uf);
+                bad |= b && (y0 + row < g.n[1]) && (x0 + c <= g.n[0]);
+#pragma unroll
+                for (int v = 0; v < NV; v++) s_flux[v][p] = F[v];
+                s_flux[NV][p] = uf;
             }
-            const bool b = hllc<3, 0, T>(g, wL, wR, F, uf);
-            bad |= b && (y0 + row < g.n[1]) && (x0 + fi <= g.n[0]);
-#pragma unroll
-            for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
-            s_flux[NV][f] = uf;
         }
         __syncthreads();
         const T idx = T(g.inv_dx[0]), idy = T(g.inv_dx[1]);
         T L[NV], divu;
         if (cell) {
-            const int f = ty * (TX + 1) + tx;
+            const int f = ty * (TX + 2) + tx;
 #pragma unroll
             for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * idx;
             divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * idx;
         }
-        // ---- y: reconstruct rows -1 .. TY of every column, then the faces
-        if constexpr (ROUTE) {
-            if constexpr (R::in_flux) __syncthreads();  // the x fluxes above are read before the area is reused
-            for (int p0 = 0; p0 < NPY; p0 += NT) {
-                const int p = p0 + tid;
-                const bool valid = p < NPY;
-                const int pc = valid ? p : NPY - 1;
-                const int li = pc % TX + NG, r = pc / TX;
-                bool lin = false;
+        // ---- y: thread p reconstructs row p / TX - 1 of column p % TX and
+        // solves the face on its + side
+        if constexpr (ROUTE && R::in_flux) __syncthreads();  // the x fluxes above are read before the area is reused
+        {
+            const int p = tid;
+            const bool valid = p < NPY;
+            const int pc = valid ? p : NPY - 1;
+            const int li = pc % TX + NG, r = pc / TX;
+            bool lin = false;
+            if constexpr (ROUTE) {
                 if (__ballot(valid))
                     lin = mlp::smooth_stencil<T>(s_mlp, scratch, &s_plane[6][r][li], &s_plane[0][r][li],
                                                  &s_plane[1][r][li], &s_plane[5][r][li], PX, sqrt_eps, logit_tau,
                                                  lane);
-                if (valid) {
-#pragma unroll
-                    for (int v = 0; v < NV; v++) {
-                        if (lin)
-                            linear5_pair<T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
-                                            s_plane[v][r + 3][li], s_plane[v][r + 4][li], s_pair[v][p],
-                                            s_pair[NV + v][p]);
-                        else
-                            weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
-                                       s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, s_pair[v][p],
-                                       s_pair[NV + v][p]);
-                    }
-                }
             }
-        } else {
-            for (int p = tid; p < NPY; p += NT) {
-                const int c = p % TX, r = p / TX;
-                const int li = c + NG;
+            if (valid) {
 #pragma unroll
-                for (int v = 0; v < NV; v++)
-                    weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li], s_plane[v][r + 3][li],
-                               s_plane[v][r + 4][li], eps, s_pair[v][p], s_pair[NV + v][p]);
+                for (int v = 0; v < NV; v++) {
+                    if (ROUTE && lin)
+                        linear5_pair<T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                        s_plane[v][r + 3][li], s_plane[v][r + 4][li], wP[v], s_minus[v][p]);
+                    else
+                        weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                   s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, wP[v], s_minus[v][p]);
+                }
             }
         }
         __syncthreads();
-        for (int f = tid; f < NFY; f += NT) {
-            const int c = f % TX, fr = f / TX;
-            const int pl = fr * TX + c;
-            T wL[NV], wR[NV], F[NV], uf;
+        {
+            const int p = tid, c = p % TX, r = p / TX;
+            if (p < NPY && r <= TY) {
+                T wR[NV], F[NV], uf;
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                wL[v] = s_pair[v][pl];
-                wR[v] = s_pair[NV + v][pl + TX];
+                for (int v = 0; v < NV; v++) wR[v] = s_minus[v][p + TX];
+                const bool b = hllc<3, 1, T>(g, wP, wR, F, uf);
+                bad |= b && (x0 + c < g.n[0]) && (y0 + r <= g.n[1]);
+#pragma unroll
+                for (int v = 0; v < NV; v++) s_flux[v][p] = F[v];
+                s_flux[NV][p] = uf;
             }
-            const bool b = hllc<3, 1, T>(g, wL, wR, F, uf);
-            bad |= b && (x0 + c < g.n[0]) && (y0 + fr <= g.n[1]);
-#pragma unroll
-            for (int v = 0; v < NV; v++) s_flux[v][f] = F[v];
-            s_flux[NV][f] = uf;
         }
         __syncthreads();
         if (cell) {
@@ -315,7 +331,7 @@ __global__ void __launch_bounds__(NT, 2)
             lxy[NV * g.vstride + c] = divu;
         }
         // the next plane overwrites s_plane (last read before the y-face
-        // barrier) and s_pair/s_flux only after two more barriers
+        // barrier), s_minus and s_flux only after one and two more barriers
     }
     if (smax_partial) {
         // workgroup maximum: wavefront butterflies, then one value per wavefront
@@ -337,24 +353,45 @@ __global__ void __launch_bounds__(NT, 2)
 // z direction + stage update.  Threads of a workgroup own a 64 x 4 block of
 // columns (64 consecutive x per wavefront: coalesced plane loads) and march
 // through kLZ planes, starting two planes early to reconstruct cell z0-1 and
-// solve face z0-1/2 without writing.
+// solve face z0-1/2 without writing.  Of the five planes of a column's
+// reconstruction window, the kRing oldest are kept in a per-thread ring in
+// LDS (each thread touches only its own slots: no barriers) and the others in
+// registers, which leaves the registers to the reconstruction and the
+// Riemann solve (the FP64 kernel spilled with the whole window in registers).
+#ifndef MFC_Z_WAVES64
+#define MFC_Z_WAVES64 2
+#endif
+#ifndef MFC_Z_WAVES32
+#define MFC_Z_WAVES32 3
+#endif
+#ifndef MFC_Z_RING
+#define MFC_Z_RING 4
+#endif
+template <class T>
+constexpr int kZWaves = sizeof(T) == 8 ? MFC_Z_WAVES64 : MFC_Z_WAVES32;
+constexpr int kRing = MFC_Z_RING, kZReg = 5 - kRing;
+static_assert(kRing >= 1 && kRing <= 4, "one to four planes in the ring");
+
 template <class T, bool ROUTE>
-__global__ void __launch_bounds__(kZX * kZY, 2)
+__global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
     k_z(Grid g, const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ lxy, int mode, double dt,
         const double *__restrict__ dt_dev, int *__restrict__ flag, const float *__restrict__ mlpw, float logit_tau,
         T sqrt_eps)
 {
-    constexpr int NV = 7, A = 6;
+    constexpr int NV = 7, A = 6, NZT = kZX * kZY;
     const T eps = T(g.eps), idz = T(g.inv_dx[2]);
-    int gx = blockIdx.x * kZX + threadIdx.x % kZX;
-    int gy = blockIdx.y * kZY + threadIdx.x / kZX;
+    int bx, by, bz;
+    tile_of_block(bx, by, bz);
+    int gx = bx * kZX + threadIdx.x % kZX;
+    int gy = by * kZY + threadIdx.x / kZX;
     const bool own = gx < g.n[0] && gy < g.n[1];
     __shared__ __align__(16) typename std::conditional<ROUTE, mlp::Params, char>::type s_mlp;
-    __shared__ __align__(16) uint16_t s_feat[ROUTE ? kZX * kZY * 16 : 1];
+    __shared__ __align__(16) uint16_t s_feat[ROUTE ? NZT * 16 : 1];
+    __shared__ T s_ring[kRing][NV][NZT];
     if constexpr (ROUTE) {
         // every lane of a wavefront takes part in the classification: lanes
         // past a ragged edge march a duplicate of the last column
-        mlp::stage_params(s_mlp, nullptr, mlpw, threadIdx.x, kZX * kZY);
+        mlp::stage_params(s_mlp, nullptr, mlpw, threadIdx.x, NZT);
         __syncthreads();
         gx = min(gx, g.n[0] - 1);
         gy = min(gy, g.n[1] - 1);
@@ -362,34 +399,41 @@ __global__ void __launch_bounds__(kZX * kZY, 2)
         return;   // no barriers in this variant
     }
     uint16_t *scratch = s_feat + (ROUTE ? (threadIdx.x / 64) * 64 * 16 : 0);
-    const int lane = threadIdx.x % 64;
-    const int z0 = blockIdx.z * kLZ<T>, z1 = min(z0 + kLZ<T>, g.n[2]);
+    const int lane = threadIdx.x % 64, t = threadIdx.x;
+    const int z0 = bz * kLZ<T>, z1 = min(z0 + kLZ<T>, g.n[2]);
     const T hdt = T(mode ? (dt_dev ? *dt_dev : dt) : 0.0);
     const T ca = T(mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0));
     const T cb = T(mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0));
     bool bad = false;
 
-    T zw[5][NV];   // primitives of planes k-1 .. k+3 after the shift
+    // window of the reconstruction of cell k+1 (planes k-1 .. k+3): plane
+    // k-1+j in ring slot rs[j] for j < kRing, else in zr[j - kRing]
+    int rs[kRing];
+    T zr[kZReg][NV];
     T pk[NV];      // cell k reconstructed at its + face
     T Fz[NV + 1];  // flux and face velocity at k-1/2
 #pragma unroll
-    for (int p = 1; p < 5; p++) bad |= load_prim3<T>(g, q, gx, gy, z0 - 4 + p, zw[p]);
+    for (int j = 0; j < kRing; j++) {
+        rs[j] = j;
+        bad |= load_prim3<T>(g, q, gx, gy, z0 - 3 + j, zr[kZReg - 1]);
+#pragma unroll
+        for (int v = 0; v < NV; v++) s_ring[j][v][t] = zr[kZReg - 1][v];
+    }
+#pragma unroll
+    for (int j = kRing; j < 4; j++) bad |= load_prim3<T>(g, q, gx, gy, z0 - 3 + j, zr[j - kRing]);
 
+    auto win = [&](int j, int v) -> T { return j < kRing ? s_ring[rs[j]][v][t] : zr[j - kRing][v]; };
     for (int k = z0 - 2; k < z1; k++) {
-#pragma unroll
-        for (int p = 0; p < 4; p++)
-#pragma unroll
-            for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
-        bad |= load_prim3<T>(g, q, gx, gy, k + 3, zw[4]);
+        bad |= load_prim3<T>(g, q, gx, gy, k + 3, zr[kZReg - 1]);
         T pn[NV], mn[NV], Fzn[NV + 1];
         bool lin = false;
         if constexpr (ROUTE) {
             T av[5], rv[5], pv[5];
 #pragma unroll
             for (int j = 0; j < 5; j++) {
-                av[j] = zw[j][A];
-                rv[j] = zw[j][0] + zw[j][1];
-                pv[j] = zw[j][5];
+                av[j] = win(j, A);
+                rv[j] = win(j, 0) + win(j, 1);
+                pv[j] = win(j, 5);
             }
             uint16_t f[16];
             mlp::features<T>(av, rv, pv, sqrt_eps, f);
@@ -397,8 +441,9 @@ __global__ void __launch_bounds__(kZX * kZY, 2)
         }
 #pragma unroll
         for (int v = 0; v < NV; v++) {
-            if (ROUTE && lin) linear5_pair<T>(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], pn[v], mn[v]);
-            else weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, pn[v], mn[v]);
+            const T w0 = win(0, v), w1 = win(1, v), w2 = win(2, v), w3 = win(3, v), w4 = win(4, v);
+            if (ROUTE && lin) linear5_pair<T>(w0, w1, w2, w3, w4, pn[v], mn[v]);
+            else weno5_pair(w0, w1, w2, w3, w4, eps, pn[v], mn[v]);
         }
         if (k >= z0 - 1) bad |= hllc<3, 2, T>(g, pk, mn, Fzn, Fzn[NV]);
 #pragma unroll
@@ -409,7 +454,7 @@ __global__ void __launch_bounds__(kZX * kZY, 2)
 #pragma unroll
             for (int v = 0; v < NV; v++) L[v] = lxy[v * g.vstride + c] + (Fz[v] - Fzn[v]) * idz;
             const T divu = lxy[NV * g.vstride + c] + (Fzn[NV] - Fz[NV]) * idz;
-            L[A] += zw[1][A] * divu;
+            L[A] += win(1, A) * divu;
             if (mode == 0) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) out[v * g.vstride + c] = L[v];
@@ -423,6 +468,18 @@ __global__ void __launch_bounds__(kZX * kZY, 2)
         }
 #pragma unroll
         for (int v = 0; v <= NV; v++) Fz[v] = Fzn[v];
+        // shift the window: plane k+kRing-1+1 (the oldest in registers)
+        // replaces plane k-1 in the ring
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            s_ring[rs[0]][v][t] = zr[0][v];
+#pragma unroll
+            for (int j = 0; j + 1 < kZReg; j++) zr[j][v] = zr[j + 1][v];
+        }
+        const int r = rs[0];
+#pragma unroll
+        for (int j = 0; j + 1 < kRing; j++) rs[j] = rs[j + 1];
+        rs[kRing - 1] = r;
     }
     if (bad) atomicOr(flag, 1);
 }
