@@ -119,7 +119,11 @@ int mfc_fill_ghosts(mfc_grid *g, void *q, void *stream);
  * filled: for every row the flux difference sum_d (F_{-1/2} - F_{+1/2})/dx_d
  * of the HLLC fluxes between WENO5 reconstructions of the primitives, plus
  * alpha1 div(u) (face-velocity divergence) on the alpha1 row.  Ghost
- * entries of rhs are not written.  q and rhs must not overlap. */
+ * entries of rhs are not written.  q and rhs must not overlap.
+ * MFC_KERNEL_SPLIT reads no ghost cell: it takes every neighbour past a face
+ * from the interior cell the ghost fill would copy there (the boundary
+ * condition applied by index), so its result is the one for filled ghosts
+ * whatever the ghost cells of q hold. */
 int mfc_rhs(mfc_grid *g, const void *q, void *rhs, void *stream);
 
 /* Largest signal speed max_cells max_d (|u_d| + c) over interior cells
@@ -128,7 +132,9 @@ int mfc_rhs(mfc_grid *g, const void *q, void *rhs, void *stream);
 int mfc_max_wavespeed(mfc_grid *g, const void *q, double *smax_host, void *stream);
 
 /* One third-order TVD (SSP) Runge-Kutta step in place on q, ghost fill
- * before every right-hand side.  If cfl > 0 the step size is
+ * before every right-hand side (MFC_KERNEL_SPLIT applies the boundary
+ * conditions by index instead, with the same result, and leaves the ghost
+ * cells of q as they were).  If cfl > 0 the step size is
  * cfl * min_d dx_d / max_wavespeed(q^n), computed on the device with no host
  * synchronisation; otherwise dt (> 0) is used.  The step size taken and the
  * accumulated time are kept on the device (mfc_time). */

@@ -105,20 +105,29 @@ __device__ __forceinline__ int64_t offset(const Grid &g, int i, int j, int k)
     return (int64_t)(k + g.off[2]) * g.stride[2] + (int64_t)(j + g.off[1]) * g.stride[1] + (i + g.off[0]);
 }
 
-// Load and convert one cell; flag only cells the method reads (at most one
-// coordinate outside the interior: out-of-grid lanes of ragged tiles may
-// touch never-written edge ghosts whose results are discarded).
+// Interior cell whose value the ghost position i (-NG <= i < n + NG) holds
+// after the ghost fill of Sec. 3.3: the adjacent interior cell
+// (extrapolation) or the cell one period away (periodic).  The split kernels
+// read every neighbour through this map and never read a ghost cell, which
+// gives the values a filled ghost layer holds, bit for bit, with no fill
+// pass.
+__device__ __forceinline__ int bc_cell(int i, int n, int lo, int hi)
+{
+    if (i < 0) return lo == MFC_BC_PERIODIC ? i + n : 0;
+    if (i >= n) return hi == MFC_BC_PERIODIC ? i - n : n - 1;
+    return i;
+}
+
+// Load and convert cell (i, j, bc_cell(k)) of a column (i, j interior).
 template <class T>
-__device__ __forceinline__ bool load_prim3(const Grid &g, const T *__restrict__ q, int i, int j, int k, T *w)
+__device__ __forceinline__ bool load_prim_z(const Grid &g, const T *__restrict__ q, int i, int j, int k, T *w)
 {
     constexpr int NV = 7;
-    const int64_t c = offset(g, i, j, k);
+    const int64_t c = offset(g, i, j, bc_cell(k, g.n[2], g.bc[4], g.bc[5]));
     T qc[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
-    const bool bad = cons_to_prim<3, T>(g, qc, w);
-    const int outside = (i < 0 || i >= g.n[0]) + (j < 0 || j >= g.n[1]) + (k < 0 || k >= g.n[2]);
-    return bad && outside <= 1;
+    return cons_to_prim<3, T>(g, qc, w);
 }
 
 // Feature exchange area of the routed reconstruction: 64 samples x 16 bf16
@@ -183,8 +192,11 @@ __global__ void __launch_bounds__(NT, 3)
         hli = c + NG;
         hlj = r < NG ? r : TY + r;
     }
-    const int ox = min(gx, xmax), oy = min(gy, ymax);
-    const int hx = min(x0 + hli - NG, xmax), hy = min(y0 + hlj - NG, ymax);
+    // cells past a ragged tile edge load a duplicate whose results are discarded
+    const int ox = bc_cell(min(gx, xmax), g.n[0], g.bc[0], g.bc[1]);
+    const int oy = bc_cell(min(gy, ymax), g.n[1], g.bc[2], g.bc[3]);
+    const int hx = bc_cell(min(x0 + hli - NG, xmax), g.n[0], g.bc[0], g.bc[1]);
+    const int hy = bc_cell(min(y0 + hlj - NG, ymax), g.n[1], g.bc[2], g.bc[3]);
     T qo[NV], qh[NV];
     auto fetch = [&](int k) {
         if (cell) {
@@ -203,11 +215,9 @@ __global__ void __launch_bounds__(NT, 3)
     for (int k = z0; k < z1; k++) {
         // ---- plane k (own cell + x/y halos) into LDS as primitives
         {
-            const int kout = k < 0 || k >= g.n[2];
             if (cell) {
                 T w[NV];
-                const int outside = (ox < 0 || ox >= g.n[0]) + (oy < 0 || oy >= g.n[1]) + kout;
-                bad |= cons_to_prim<3, T>(g, qo, w) && outside <= 1;
+                bad |= cons_to_prim<3, T>(g, qo, w);
 #pragma unroll
                 for (int v = 0; v < NV; v++) s_plane[v][ty + NG][tx + NG] = w[v];
                 if (smax_partial && own) {
@@ -220,8 +230,7 @@ __global__ void __launch_bounds__(NT, 3)
             }
             if (halo) {
                 T w[NV];
-                const int outside = (hx < 0 || hx >= g.n[0]) + (hy < 0 || hy >= g.n[1]) + kout;
-                bad |= cons_to_prim<3, T>(g, qh, w) && outside <= 1;
+                bad |= cons_to_prim<3, T>(g, qh, w);
 #pragma unroll
                 for (int v = 0; v < NV; v++) s_plane[v][hlj][hli] = w[v];
             }
@@ -415,16 +424,16 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
 #pragma unroll
     for (int j = 0; j < kRing; j++) {
         rs[j] = j;
-        bad |= load_prim3<T>(g, q, gx, gy, z0 - 3 + j, zr[kZReg - 1]);
+        bad |= load_prim_z<T>(g, q, gx, gy, z0 - 3 + j, zr[kZReg - 1]);
 #pragma unroll
         for (int v = 0; v < NV; v++) s_ring[j][v][t] = zr[kZReg - 1][v];
     }
 #pragma unroll
-    for (int j = kRing; j < 4; j++) bad |= load_prim3<T>(g, q, gx, gy, z0 - 3 + j, zr[j - kRing]);
+    for (int j = kRing; j < 4; j++) bad |= load_prim_z<T>(g, q, gx, gy, z0 - 3 + j, zr[j - kRing]);
 
     auto win = [&](int j, int v) -> T { return j < kRing ? s_ring[rs[j]][v][t] : zr[j - kRing][v]; };
     for (int k = z0 - 2; k < z1; k++) {
-        bad |= load_prim3<T>(g, q, gx, gy, k + 3, zr[kZReg - 1]);
+        bad |= load_prim_z<T>(g, q, gx, gy, k + 3, zr[kZReg - 1]);
         T pn[NV], mn[NV], Fzn[NV + 1];
         bool lin = false;
         if constexpr (ROUTE) {

@@ -166,3 +166,34 @@ def test_full_size_256_sampled(prec, kernel):
     err = dt * np.abs(rg - ro).max(axis=0) / scale
     say(f"    {len(cells)} cells, forward-Euler-step error per variable {err}")
     assert err.max() <= (1e-12 if prec == "fp64" else 2e-6), err
+
+
+# ------------------------------------------- boundary conditions by index
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0, 0, 0), (1, 1, 1, 1, 1, 1), (1, 1, 0, 0, 1, 1)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_split_reads_no_ghost_cell(bc, prec):
+    """The split kernels take neighbours past a face from the interior cell
+    the ghost fill would copy there: with every ghost cell set to NaN the
+    right-hand side and the step are bitwise those of a filled state, and the
+    step leaves the ghost cells as they were."""
+    spec, w = W.bubble_collapse_3d(n=(17, 15, 17))   # ragged in every tile dimension
+    spec = dataclasses.replace(spec, bc=bc)
+    say(f"[split bc by index] bc={bc} {prec}")
+    P = mfc.MFC_FP64 if prec == "fp64" else mfc.MFC_FP32_MIXED
+    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_SPLIT, precision=P)
+    q = s.state_from_prim(w)
+    s.fill_ghosts(q)
+    ghost = torch.ones(q.shape, dtype=torch.bool, device=q.device)
+    ghost[spec.interior] = False
+    qn = q.clone()
+    qn[ghost] = float("nan")
+    I = (slice(None),) + spec.interior[1:]
+    r1, r2 = s.rhs(q), s.rhs(qn)
+    s.check()
+    assert torch.equal(r1[I], r2[I])
+    s.step(q, cfl=0.3)
+    s.step(qn, cfl=0.3)
+    s.check()
+    assert torch.equal(q[I], qn[I])
+    assert torch.isnan(qn[ghost]).all()
