@@ -376,10 +376,16 @@ __global__ void __launch_bounds__(NT, 3)
 #ifndef MFC_Z_RING
 #define MFC_Z_RING 4
 #endif
+#ifndef MFC_Z_RING_ROUTE
+#define MFC_Z_RING_ROUTE 1
+#endif
 template <class T>
 constexpr int kZWaves = sizeof(T) == 8 ? MFC_Z_WAVES64 : MFC_Z_WAVES32;
-constexpr int kRing = MFC_Z_RING, kZReg = 5 - kRing;
-static_assert(kRing >= 1 && kRing <= 4, "one to four planes in the ring");
+// the routed variant keeps LDS for the network and its feature exchange
+template <bool ROUTE>
+constexpr int kRing = ROUTE ? MFC_Z_RING_ROUTE : MFC_Z_RING;
+static_assert(kRing<false> >= 1 && kRing<false> <= 4 && kRing<true> >= 1 && kRing<true> <= 4,
+              "one to four planes in the ring");
 
 template <class T, bool ROUTE>
 __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
@@ -387,6 +393,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
         const double *__restrict__ dt_dev, int *__restrict__ flag, const float *__restrict__ mlpw, float logit_tau,
         T sqrt_eps)
 {
+    constexpr int kRing = mfc::kRing<ROUTE>, kZReg = 5 - kRing;
     constexpr int NV = 7, A = 6, NZT = kZX * kZY;
     const T eps = T(g.eps), idz = T(g.inv_dx[2]);
     int bx, by, bz;
