@@ -4,9 +4,10 @@
 
 Workload: the 3D air-bubble collapse in water on 128^3 cells (7 state
 variables, FP64, CFL 0.3, seeded spherical-harmonic surface noise), state
-resident in HBM.  A step is one full SSP-RK3 step: ghost fill, the CFL
-wave-speed reduction and three right-hand-side evaluations, each with its
-stage update.  The metric is RHS cell-updates/s = interior cells x 3 stages
+resident in HBM.  A step is one full SSP-RK3 step: the CFL wave-speed
+reduction and three right-hand-side evaluations, each with its stage update
+and boundary conditions (the split path applies them by index; the other
+paths fill ghost layers first).  The metric is RHS cell-updates/s = interior cells x 3 stages
 x steps / wall time.
 
 One JSON line is printed.  `roofline` is measured on the dominant kernel (the
@@ -49,14 +50,16 @@ SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences)", flops
          1: dict(name="k_z (z reconstruction, HLLC, source, stage update)", flops=2416 - 1601,
                  bytes=56 + 64 + 56 * 2 / 3 + 56)}
 # Measured HBM traffic per launch (bytes) of the split path's kernels on the
-# 128^3 FP64 bubble: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each
+# 128^3 bubble: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each
 # scaled by its reading for a copy kernel of known size (FETCH_SIZE x 2.00,
 # WRITE_SIZE x 1.00).  Valid only for the kernel sources they were taken on;
 # any change to those files turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h")
-TRAFFIC = {"sha256": "265254c84f13ca9810372af922bcfa9580b2677b00e4c742dae235cf68bfd97a",
-           ("split", "fp64", 128, 0): (277.60e6, 167.80e6),
-           ("split", "fp64", 128, 1): (651.10e6, 127.40e6)}
+TRAFFIC = {"sha256": "c00d3e6ff8a667b396811eb0b18a458220cd7cbd50bb67654e720a55a9eecfbe",
+           ("split", "fp64", 128, 0): (124.72e6, 139.42e6),
+           ("split", "fp64", 128, 1): (508.30e6, 121.61e6),
+           ("split", "fp32", 128, 0): (61.78e6, 70.32e6),
+           ("split", "fp32", 128, 1): (248.26e6, 61.55e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
