@@ -65,9 +65,12 @@ PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
 
 
-def measured_traffic(kernel, precision, n, slot):
-    """(read, write) HBM bytes per launch from the counter runs, or None."""
+def measured_traffic(kernel, precision, recon, n, slot):
+    """(read, write) HBM bytes per launch from the counter runs (WENO5
+    kernels only), or None."""
     import hashlib
+    if recon != "weno5":
+        return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_2305_09163_amd", "csrc", f), "rb") as fh:
@@ -289,7 +292,7 @@ def main():
              "frac": achieved / peak_alu, "traffic": None}
         if bound == "hbm":
             r.update(achieved=hbm / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=hbm / PEAK_HBM)
-        tr = measured_traffic(args.kernel, args.precision, args.n, slot)
+        tr = measured_traffic(args.kernel, args.precision, args.recon, args.n, slot)
         if tr:
             # measured HBM bytes per launch over the same average launch duration
             r.update(traffic=sum(tr) / avg / 1e9, traffic_unit="GB/s",
