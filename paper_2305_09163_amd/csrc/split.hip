@@ -376,11 +376,19 @@ __global__ void __launch_bounds__(NT, 3)
 #ifndef MFC_Z_RING
 #define MFC_Z_RING 4
 #endif
+#ifndef MFC_Z_EARLY64
+#define MFC_Z_EARLY64 0
+#endif
+#ifndef MFC_Z_EARLY32
+#define MFC_Z_EARLY32 1
+#endif
 #ifndef MFC_Z_RING_ROUTE
 #define MFC_Z_RING_ROUTE 1
 #endif
 template <class T>
 constexpr int kZWaves = sizeof(T) == 8 ? MFC_Z_WAVES64 : MFC_Z_WAVES32;
+template <class T>
+constexpr bool kZEarly = sizeof(T) == 8 ? MFC_Z_EARLY64 : MFC_Z_EARLY32;
 // the routed variant keeps LDS for the network and its feature exchange
 template <bool ROUTE>
 constexpr int kRing = ROUTE ? MFC_Z_RING_ROUTE : MFC_Z_RING;
@@ -441,6 +449,24 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
     auto win = [&](int j, int v) -> T { return j < kRing ? s_ring[rs[j]][v][t] : zr[j - kRing][v]; };
     for (int k = z0 - 2; k < z1; k++) {
         bad |= load_prim_z<T>(g, q, gx, gy, k + 3, zr[kZReg - 1]);
+        // FP32: the operands of the stage update of cell k are loaded before
+        // the reconstruction so that their latency overlaps it (the FP64
+        // kernel has no registers to spare for them and loads them late)
+        T lx[NV + 1], qa[NV], qb[NV];
+        if constexpr (kZEarly<T>) {
+            if (k >= z0 && own) {
+                const int64_t c = offset(g, gx, gy, k);
+#pragma unroll
+                for (int v = 0; v <= NV; v++) lx[v] = lxy[v * g.vstride + c];
+                if (mode != 0) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        qa[v] = q0[v * g.vstride + c];
+                        qb[v] = q[v * g.vstride + c];
+                    }
+                }
+            }
+        }
         T pn[NV], mn[NV], Fzn[NV + 1];
         bool lin = false;
         if constexpr (ROUTE) {
@@ -466,10 +492,16 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
         for (int v = 0; v < NV; v++) pk[v] = pn[v];
         if (k >= z0 && own) {
             const int64_t c = offset(g, gx, gy, k);
-            T L[NV];
+            T L[NV], divu;
+            if constexpr (kZEarly<T>) {
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] = lxy[v * g.vstride + c] + (Fz[v] - Fzn[v]) * idz;
-            const T divu = lxy[NV * g.vstride + c] + (Fzn[NV] - Fz[NV]) * idz;
+                for (int v = 0; v < NV; v++) L[v] = lx[v] + (Fz[v] - Fzn[v]) * idz;
+                divu = lx[NV] + (Fzn[NV] - Fz[NV]) * idz;
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; v++) L[v] = lxy[v * g.vstride + c] + (Fz[v] - Fzn[v]) * idz;
+                divu = lxy[NV * g.vstride + c] + (Fzn[NV] - Fz[NV]) * idz;
+            }
             L[A] += win(1, A) * divu;
             if (mode == 0) {
 #pragma unroll
@@ -478,7 +510,8 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     const int64_t o = v * g.vstride + c;
-                    out[o] = ca * q0[o] + cb * (q[o] + hdt * L[v]);
+                    if constexpr (kZEarly<T>) out[o] = ca * qa[v] + cb * (qb[v] + hdt * L[v]);
+                    else out[o] = ca * q0[o] + cb * (q[o] + hdt * L[v]);
                 }
             }
         }
