@@ -340,11 +340,15 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
 #pragma unroll
                 for (int v = 0; v < NV; v++) out[v * g.vstride + c] = L[v];
             } else {
+                // every operand before the first store (out may alias q0)
+                T a0[NV], a1[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
-                    const int64_t o = v * g.vstride + c;
-                    out[o] = ca * q0[o] + cb * (q[o] + hdt * L[v]);
+                    a0[v] = q0[v * g.vstride + c];
+                    a1[v] = q[v * g.vstride + c];
                 }
+#pragma unroll
+                for (int v = 0; v < NV; v++) out[v * g.vstride + c] = ca * a0[v] + cb * (a1[v] + hdt * L[v]);
             }
         }
     }

@@ -147,8 +147,14 @@ struct RouteLds {
 // quantity of the CFL condition (Sec. 1), and writes one maximum per
 // workgroup: the step size is then set between this launch and the z pass,
 // which is the first to use it.
+#ifndef MFC_XY_WAVES32
+#define MFC_XY_WAVES32 5
+#endif
+template <class T>
+constexpr int kXYWaves = sizeof(T) == 8 ? 3 : MFC_XY_WAVES32;
+
 template <class T, bool ROUTE>
-__global__ void __launch_bounds__(NT, 3)
+__global__ void __launch_bounds__(NT, kXYWaves<T>)
     k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag,
          const float *__restrict__ mlpw, float logit_tau, T sqrt_eps, double *__restrict__ smax_partial)
 {
@@ -507,12 +513,18 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
 #pragma unroll
                 for (int v = 0; v < NV; v++) out[v * g.vstride + c] = L[v];
             } else {
+                if constexpr (!kZEarly<T>) {
+                    // every operand before the first store: out may alias q0
+                    // (the last stage updates q^n in place), so a store
+                    // would otherwise hold back the next variable's loads
 #pragma unroll
-                for (int v = 0; v < NV; v++) {
-                    const int64_t o = v * g.vstride + c;
-                    if constexpr (kZEarly<T>) out[o] = ca * qa[v] + cb * (qb[v] + hdt * L[v]);
-                    else out[o] = ca * q0[o] + cb * (q[o] + hdt * L[v]);
+                    for (int v = 0; v < NV; v++) {
+                        qa[v] = q0[v * g.vstride + c];
+                        qb[v] = q[v * g.vstride + c];
+                    }
                 }
+#pragma unroll
+                for (int v = 0; v < NV; v++) out[v * g.vstride + c] = ca * qa[v] + cb * (qb[v] + hdt * L[v]);
             }
         }
 #pragma unroll

@@ -131,11 +131,15 @@ __global__ void __launch_bounds__(kThreads) k_update(Grid g, const double *__res
     const double h = dt_dev ? *dt_dev : dt;
     const double a = mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0);
     const double bb = mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0);
+    // every operand before the first store (out may alias q0)
+    double a0[NV], a1[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-        int64_t o = v * g.vstride + c;
-        out[o] = a * q0[o] + bb * (q[o] + h * L[v]);
+        a0[v] = q0[v * g.vstride + c];
+        a1[v] = q[v * g.vstride + c];
     }
+#pragma unroll
+    for (int v = 0; v < NV; v++) out[v * g.vstride + c] = a * a0[v] + bb * (a1[v] + h * L[v]);
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
