@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
 
 KERNELS = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}
 DEFAULT_KERNEL = mfc.MFC_KERNEL_FUSED
+BENCH_KERNEL = mfc.MFC_KERNEL_SPLIT     # the path bench.py times
 
 
 def say(*a):
@@ -170,6 +171,43 @@ def test_bubble_3d_steps_parity(kernel):
     assert rel_linf(host(q), qo, spec).max() <= 1e-10
 
 
+def test_bubble_3d_200_steps_parity():
+    """3D bubble collapse at 32^3, 200 steps at CFL 0.3 on the benchmark
+    path: relative L1 within 1e-10 of the oracle, and the same simulated
+    time."""
+    spec, w = W.bubble_collapse_3d(n=32)
+    say("[rk3 200 steps] bubble_3d_32 kernel=split")
+    s = mfc.Solver(spec, kernel=BENCH_KERNEL)
+    q = gpu_state(s, w)
+    s.run(q, 200, cfl=0.3)
+    t, _ = s.time()
+    s.check()
+    qo, to, st = oracle.run(spec, oracle.prim_to_cons_field(spec, w), 200, cfl=0.3)
+    assert st == oracle.OK
+    assert t == pytest.approx(to, rel=1e-11)
+    err = rel_l1(host(q), qo, spec, floor_mom=acoustic_floor(spec, oracle.prim_to_cons_field(spec, w)))
+    say(f"    rel L1 per variable {err}")
+    assert err.max() <= 1e-10, err
+
+
+def test_full_size_bubble_one_step_parity():
+    """The 128^3 bubble-collapse workload: one SSP-RK3 step at CFL 0.3 in the
+    launch configuration the benchmark times, relative L-infinity within
+    1e-12 of the oracle."""
+    spec, w = W.bubble_collapse_3d(n=128)
+    say("[rk3 1 step full size] bubble_3d_128 kernel=split")
+    s = mfc.Solver(spec, kernel=BENCH_KERNEL)
+    q = gpu_state(s, w)
+    s.step(q, cfl=0.3)
+    s.check()
+    qi = oracle.prim_to_cons_field(spec, w)
+    qo, _, st = oracle.run(spec, qi, 1, cfl=0.3)
+    assert st == oracle.OK
+    err = rel_linf(host(q), qo, spec, floor_mom=acoustic_floor(spec, qi))
+    say(f"    rel Linf per variable {err}")
+    assert err.max() <= 1e-12, err
+
+
 def test_max_wavespeed_parity():
     for name in ["shock_tube_400", "droplet_2d_45x45", "bubble_3d_37x21x19"]:
         spec, w = workload(name)
@@ -181,13 +219,14 @@ def test_max_wavespeed_parity():
         assert sm == pytest.approx(so, rel=1e-14)
 
 
-def test_full_size_bubble_rhs_parity():
+@pytest.mark.parametrize("kernel", ["split", "fused"])
+def test_full_size_bubble_rhs_parity(kernel):
     """The 128^3 bubble-collapse workload: one full right-hand side (every
-    interior cell) against the oracle, in the launch configuration the
-    benchmark times."""
+    interior cell) against the oracle; the split path is the launch
+    configuration the benchmark times."""
     spec, w = W.bubble_collapse_3d(n=128)
-    say("[rhs full size] bubble_3d_128")
-    s = mfc.Solver(spec, kernel=DEFAULT_KERNEL)
+    say(f"[rhs full size] bubble_3d_128 kernel={kernel}")
+    s = mfc.Solver(spec, kernel=KERNELS[kernel])
     q = gpu_state(s, w)
     s.fill_ghosts(q)
     r = host(s.rhs(q))
