@@ -65,11 +65,11 @@ PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
 
 
-def measured_traffic(kernel, precision, recon, n, slot):
+def measured_traffic(kernel, precision, recon, model, n, slot):
     """(read, write) HBM bytes per launch from the counter runs (WENO5
     kernels only), or None."""
     import hashlib
-    if recon != "weno5":
+    if recon != "weno5" or model != "allaire":
         return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -208,6 +208,8 @@ def main():
                     help="bubble: the 3D bubble collapse (default); ensemble: 64 uneven 2D droplet-shock runs")
     ap.add_argument("--recon", choices=["weno5", "learned"], default="weno5",
                     help="learned: reconstruction routed by the trained indicator (weights from --weights)")
+    ap.add_argument("--model", choices=["allaire", "kapila"], default="allaire",
+                    help="volume-fraction equation: Allaire (default) or Kapila (with the K div(u) source)")
     ap.add_argument("--tau", type=float, default=None,
                     help="routing threshold on P(smooth) (default: the one stored beside the weights, else 0.5)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2305_09163_amd", "indicator_weights.npy"))
@@ -230,6 +232,9 @@ def main():
     if args.workload == "ensemble":
         return bench_ensemble(args, torch, mfc, W)
     spec, w = W.bubble_collapse_3d(n=args.n)
+    if args.model == "kapila":
+        import dataclasses
+        spec = dataclasses.replace(spec, model=1)
     kernel = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}[args.kernel]
     precision = mfc.MFC_FP64 if args.precision == "fp64" else mfc.MFC_FP32_MIXED
     learned = args.recon == "learned"
@@ -292,7 +297,7 @@ def main():
              "frac": achieved / peak_alu, "traffic": None}
         if bound == "hbm":
             r.update(achieved=hbm / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=hbm / PEAK_HBM)
-        tr = measured_traffic(args.kernel, args.precision, args.recon, args.n, slot)
+        tr = measured_traffic(args.kernel, args.precision, args.recon, args.model, args.n, slot)
         if tr:
             # measured HBM bytes per launch over the same average launch duration
             r.update(traffic=sum(tr) / avg / 1e9, traffic_unit="GB/s",
@@ -317,6 +322,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": f"bubble_collapse_3d_{args.n}", "cells": spec.cells, "nvar": spec.nvar,
                       "cfl": cfl, "precision": args.precision, "kernel": args.kernel, "recon": args.recon,
+                      "model": args.model,
                       "parallelism": "single GPU"},
            "roofline": roof, "simulated_time_s": t}
     if learned:

@@ -5,8 +5,9 @@
  * The operations are those of the paper's numerical method:
  *   - governing equations (Sec. 2.1): partial densities alpha1 rho1 and
  *     alpha2 rho2, mixture momentum, total energy, and the volume fraction
- *     alpha1 advected with the non-conservative alpha1 div(u) term (Allaire
- *     form: the K div(u) term of the Kapila model is dropped);
+ *     alpha1 advected with the non-conservative alpha1 div(u) term; the
+ *     Allaire form (K div(u) dropped, the default) or the Kapila form
+ *     (u . grad(alpha1) = K div(u), MFC_MODEL_KAPILA);
  *   - stiffened-gas EOS per fluid (Sec. 2.1, eq. soe) mixed at pressure
  *     equilibrium: rho E = Gamma p + Pi + rho |u|^2/2 with
  *     Gamma = sum alpha_k/(gamma_k - 1), Pi = sum alpha_k gamma_k pi_k/(gamma_k - 1);
@@ -60,6 +61,18 @@ enum { MFC_BC_EXTRAP = 0, MFC_BC_PERIODIC = 1 };
 enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
 enum { MFC_RECON_WENO5 = 0, MFC_RECON_LEARNED = 1 };
 
+/* Volume-fraction equation (Sec. 2.1).  Allaire: d(alpha1)/dt + u . grad(alpha1)
+ * = 0, i.e. the alpha1 row of eq. (fvmdis) carries alpha1_cell div(u).
+ * Kapila: d(alpha1)/dt + u . grad(alpha1) = K div(u) with
+ * K = (rho2 c2^2 - rho1 c1^2) / (rho2 c2^2/alpha2 + rho1 c1^2/alpha1) and
+ * rho_k c_k^2 = gamma_k (p + pi_k) at the cell's pressure (the paper's
+ * rho1 c2^2 in the denominator read as rho1 c1^2), so the alpha1 row carries
+ * (alpha1 + K)_cell div(u); K = 0 where alpha1 or alpha2 is not positive.
+ * The Kapila form can lose positivity of alpha at strong material
+ * interfaces (the paper notes its numerical instability); such cells are
+ * reported like any non-physical state. */
+enum { MFC_MODEL_ALLAIRE = 0, MFC_MODEL_KAPILA = 1 };
+
 /* Kernel implementation of the right-hand side. */
 enum {
     MFC_KERNEL_FUSED = 0,   /* one fused pass per stage (default)                    */
@@ -85,6 +98,7 @@ typedef struct {
                             right-hand side)                                       */
     double weno_eps;     /* WENO5-JS epsilon, > 0 (1e-6 in the paper's setting)    */
     int kernel;          /* MFC_KERNEL_*                                           */
+    int model;           /* MFC_MODEL_ALLAIRE or MFC_MODEL_KAPILA                  */
 } mfc_grid_desc;
 
 /* Create a grid handle from *desc (validated; see mfc_grid_desc) and

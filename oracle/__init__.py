@@ -41,7 +41,7 @@ class _Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3),
                 ("gamma", ctypes.c_double * 2), ("pi_inf", ctypes.c_double * 2), ("bc", ctypes.c_int * 6),
                 ("weno_eps", ctypes.c_double), ("recon", ctypes.c_int),
-                ("smooth", ctypes.POINTER(ctypes.c_ubyte))]
+                ("smooth", ctypes.POINTER(ctypes.c_ubyte)), ("model", ctypes.c_int)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -62,6 +62,7 @@ def lib():
             "ora_padded_cells": (ctypes.c_int64, [G]),
             "ora_mixture": (None, [G, ctypes.c_double, _D, _D]),
             "ora_sound_speed2": (ctypes.c_double, [G, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+            "ora_kapila_K": (ctypes.c_double, [G, _D]),
             "ora_prim_to_cons": (None, [G, _D, _D]),
             "ora_cons_to_prim": (ctypes.c_int, [G, _D, _D]),
             "ora_weno5": (None, [_D, ctypes.c_double, _D, _D, _D]),
@@ -85,6 +86,7 @@ def lib():
 
 
 RECON_WENO5, RECON_LINEAR, RECON_MASK = 0, 1, 2
+MODEL_ALLAIRE, MODEL_KAPILA = 0, 1
 
 
 def grid(spec, recon: int = RECON_WENO5, smooth=None) -> _Grid:
@@ -105,6 +107,7 @@ def grid(spec, recon: int = RECON_WENO5, smooth=None) -> _Grid:
     for f in range(6):
         g.bc[f] = spec.bc[f]
     g.weno_eps = spec.weno_eps
+    g.model = getattr(spec, "model", MODEL_ALLAIRE)
     return g
 
 
@@ -175,6 +178,14 @@ def prim_to_cons_field(spec, w):
     q = np.empty_like(w)
     lib().ora_prim_to_cons_field(ctypes.byref(grid(spec)), _ptr(w), _ptr(q))
     return q
+
+
+def kapila_K(spec, w_cell):
+    """K of the Kapila volume-fraction equation for one cell's primitive
+    vector (nvar values)."""
+    w = _arr(w_cell)
+    assert w.shape == (spec.nvar,)
+    return lib().ora_kapila_K(ctypes.byref(grid(spec)), _ptr(w))
 
 
 def cons_to_prim_field(spec, q):

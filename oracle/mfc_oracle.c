@@ -64,6 +64,8 @@ typedef struct {
     const unsigned char *smooth; /* recon 2: smooth[d * padded cells + c]
                            != 0 selects the linear stencil for every
                            variable of padded cell c along direction d    */
+    int model;          /* 0 Allaire (alpha1 equation without K div(u));
+                           1 Kapila (with K div(u))                       */
 } ora_grid;
 
 int ora_nvar(int ndim) { return 4 + ndim; }
@@ -108,6 +110,27 @@ double ora_sound_speed2(const ora_grid *g, double rho, double p, double alpha1)
     double Gamma, Pi;
     ora_mixture(g, alpha1, &Gamma, &Pi);
     return ((Gamma + 1.0) * p + Pi) / (Gamma * rho);
+}
+
+/* K of the Kapila model's volume-fraction equation (Sec. 2.1):
+ *   K = (rho2 c2^2 - rho1 c1^2) / (rho2 c2^2/alpha2 + rho1 c1^2/alpha1),
+ * (the paper prints rho1 c2^2 in the second denominator term; the model's
+ * derivation, equal phase pressure rates under compression, needs
+ * rho1 c1^2), with the phase densities rho_k = (alpha_k rho_k)/alpha_k and
+ * the stiffened-gas phase sound speeds c_k^2 = gamma_k (p + pi_k)/rho_k at
+ * the common pressure p.  w is one cell's primitive vector.  K is 0 where a
+ * volume fraction is not positive (the pure-phase limit). */
+double ora_kapila_K(const ora_grid *g, const double *w)
+{
+    int nv = ora_nvar(g->ndim);
+    double alpha1 = w[nv - 1], alpha2 = 1.0 - alpha1, p = w[nv - 2];
+    if (!(alpha1 > 0.0) || !(alpha2 > 0.0))
+        return 0.0;
+    double rho1 = w[0] / alpha1, rho2 = w[1] / alpha2;
+    double c1sq = g->gamma[0] * (p + g->pi_inf[0]) / rho1;
+    double c2sq = g->gamma[1] * (p + g->pi_inf[1]) / rho2;
+    double z1 = rho1 * c1sq, z2 = rho2 * c2sq;
+    return (z2 - z1) / (z2 / alpha2 + z1 / alpha1);
 }
 
 static int nonphysical(double rho, double c2)
@@ -355,7 +378,9 @@ int ora_fill_ghosts(const ora_grid *g, double *q)
  *   alpha1 row: the same flux difference of alpha1 u plus
  *               alpha1_cell * div(u), div(u) = sum_d (u_{+1/2} - u_{-1/2})/dx_d,
  * i.e. eq. (fvm) with s = 0 and h = -alpha1 on the alpha1 row, which is
- * the Allaire model's u . grad(alpha1) = div(alpha1 u) - alpha1 div(u).
+ * the Allaire model's u . grad(alpha1) = div(alpha1 u) - alpha1 div(u);
+ * with model 1 (Kapila) the alpha1 row carries (alpha1 + K)_cell div(u),
+ * i.e. h = -(alpha1 + K), from u . grad(alpha1) = K div(u).
  * Ghost entries of rhs are not written. */
 int ora_rhs(const ora_grid *g, const double *q, double *rhs)
 {
@@ -444,11 +469,20 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                 }
             }
     }
-    /* non-conservative source: -h div(u) with h = -alpha1 on the alpha1 row */
+    /* non-conservative source: -h div(u) with h = -alpha1 (Allaire) or
+     * h = -(alpha1 + K) (Kapila) on the alpha1 row */
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < ny; j++)
-            for (int i = 0; i < nx; i++)
-                rhs[at(g, nv - 1, i, j, k)] += w[at(g, nv - 1, i, j, k)] * divu[at(g, 0, i, j, k)];
+            for (int i = 0; i < nx; i++) {
+                double h = w[at(g, nv - 1, i, j, k)];
+                if (g->model == 1) {
+                    double wc[MAXV];
+                    for (int v = 0; v < nv; v++)
+                        wc[v] = w[at(g, v, i, j, k)];
+                    h += ora_kapila_K(g, wc);
+                }
+                rhs[at(g, nv - 1, i, j, k)] += h * divu[at(g, 0, i, j, k)];
+            }
 
     free(w); free(divu); free(rp); free(rm); free(Ff); free(uf);
     return status;

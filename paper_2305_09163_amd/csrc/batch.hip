@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kBT, 2)
                   int nitems, const double *__restrict__ scal, int stage, int xcd, int *__restrict__ flag)
 {
     using S = Tile2<TX, TY, T>;
-    constexpr int NV = 6, A = 5;
+    constexpr int NV = 6, A = 5, E = 4;
     static_assert(TX * TY == kBT, "one cell per thread");
     __shared__ T s_plane[NV][S::PY][S::PX];
     __shared__ T s_pair[2 * NV][S::NP];
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(kBT, 2)
             for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * idy;
             divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
         }
-        L[A] += wk[A] * divu;
+        L[A] += alpha_source<T>(g, wk[A], wk[E]) * divu;
         if (own) {
             const int64_t c = (int64_t)(gy + NG) * g.stride[1] + (gx + NG);
             // every operand before the first store (out may alias q0)
@@ -505,6 +505,7 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
         if (d.precision != MFC_FP64 && d.precision != MFC_FP32_MIXED) return fail(MFC_E_ARG, "unknown precision");
         if (d.num_fluids != 2) return fail(MFC_E_UNSUPPORTED, "num_fluids must be 2");
         if (d.recon != MFC_RECON_WENO5) return fail(MFC_E_UNSUPPORTED, "batched runs use WENO5");
+        if (d.model != MFC_MODEL_ALLAIRE && d.model != MFC_MODEL_KAPILA) return fail(MFC_E_ARG, "unknown model");
         for (int k = 0; k < 2; k++) {
             if (d.n[k] < 3 || d.n[k] > (1 << 15)) return fail(MFC_E_ARG, "n must be in [3, 32768]");
             if (!(d.hi[k] > d.lo[k])) return fail(MFC_E_ARG, "hi must exceed lo");
@@ -556,6 +557,7 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
         g.h1 = d.gamma[0] * d.pi_inf[0] / (d.gamma[0] - 1.0);
         g.h2 = d.gamma[1] * d.pi_inf[1] / (d.gamma[1] - 1.0);
         g.eps = d.weno_eps;
+        set_kapila(g, d);
         b->grids.push_back(g);
         dxmin[r] = g.dxmin;
         b->cells += (int64_t)g.n[0] * g.n[1];

@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
 #pragma unroll
             for (int v = 0; v <= NV; v++) Fz[v] = Fzn[v];
         }
-        L[A] += wk[A] * divu;
+        L[A] += alpha_source<T>(g, wk[A], wk[E]) * divu;
 
         if (own) {
             const int64_t c = (int64_t)(k + g.off[2]) * g.stride[2] + (int64_t)(gy + g.off[1]) * g.stride[1] +

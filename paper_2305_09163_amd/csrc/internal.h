@@ -48,6 +48,8 @@ constexpr int kReduceThreads = 256;
 
 // status helpers
 int fail(int status, const std::string &detail);
+// Kapila coefficients of a grid from its descriptor (model, gamma, pi_inf)
+void set_kapila(Grid &g, const mfc_grid_desc &d);
 int hip_status(hipError_t e, const char *what);
 
 // kernel timing: bracket one launch of the dominant kernel

@@ -47,6 +47,15 @@ void timing_end(mfc_grid *h, hipStream_t s, int slot)
     h->ev_used[slot] += 2;
 }
 
+void set_kapila(Grid &g, const mfc_grid_desc &d)
+{
+    g.kapila = d.model == MFC_MODEL_KAPILA;
+    for (int k = 0; k < 2; k++) {
+        g.zg[k] = d.gamma[k];
+        g.zp[k] = d.gamma[k] * d.pi_inf[k];
+    }
+}
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -238,6 +247,7 @@ int validate(const mfc_grid_desc *d)
     if (!(d->weno_eps > 0.0)) return fail(MFC_E_ARG, "weno_eps must be > 0");
     if (d->precision != MFC_FP64 && d->precision != MFC_FP32_MIXED) return fail(MFC_E_ARG, "unknown precision");
     if (d->recon != MFC_RECON_WENO5 && d->recon != MFC_RECON_LEARNED) return fail(MFC_E_ARG, "unknown recon");
+    if (d->model != MFC_MODEL_ALLAIRE && d->model != MFC_MODEL_KAPILA) return fail(MFC_E_ARG, "unknown model");
     if (d->kernel != MFC_KERNEL_FUSED && d->kernel != MFC_KERNEL_STAGED && d->kernel != MFC_KERNEL_SPLIT)
         return fail(MFC_E_ARG, "unknown kernel");
     if (d->precision == MFC_FP32_MIXED && d->kernel == MFC_KERNEL_STAGED)
@@ -399,6 +409,7 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
     g.h2 = desc->gamma[1] * desc->pi_inf[1] / (desc->gamma[1] - 1.0);
     g.eps = desc->weno_eps;
     for (int f = 0; f < 6; f++) g.bc[f] = h->desc.bc[f];
+    set_kapila(g, *desc);
     h->cells_padded = g.vstride;
     h->cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
     if (hipGetDevice(&h->device) != hipSuccess ||

@@ -36,6 +36,9 @@ struct Grid {
     double g1, g2, h1, h2;
     double eps;       // WENO epsilon
     int bc[6];        // boundary kind per face (x-, x+, y-, y+, z-, z+): MFC_BC_*
+    // Kapila alpha1 equation (kapila != 0): rho_k c_k^2 = zg[k] p + zp[k]
+    int kapila;
+    double zg[2], zp[2];  // gamma_k and gamma_k pi_k
 };
 
 // ---------------------------------------------------------------- reciprocal
@@ -133,6 +136,23 @@ __device__ __forceinline__ void prim_to_cons(const Grid &g, const T *w, T *q)
     }
     q[E] = T(Gam * double(w[E]) + Pi + 0.5 * rho * u2);
     q[A] = w[A];
+}
+
+// --------------------------------------------------------- Kapila source
+// Coefficient h of the alpha1 row's non-conservative term h div(u)
+// (eq. fvmdis with h(q) of eq. fvm negated): alpha1 for the Allaire model,
+// alpha1 + K for the Kapila model (Sec. 2.1), with
+//   K = (Z2 - Z1) / (Z2/alpha2 + Z1/alpha1),  Z_k = rho_k c_k^2 = gamma_k (p + pi_k)
+// for stiffened-gas phases at the common pressure p; K = 0 where a volume
+// fraction is not positive.
+template <class T>
+__device__ __forceinline__ T alpha_source(const Grid &g, T alpha1, T p)
+{
+    if (!g.kapila) return alpha1;
+    const T alpha2 = T(1) - alpha1;
+    if (!(alpha1 > T(0)) || !(alpha2 > T(0))) return alpha1;
+    const T z1 = fmaT(T(g.zg[0]), p, T(g.zp[0])), z2 = fmaT(T(g.zg[1]), p, T(g.zp[1]));
+    return alpha1 + (z2 - z1) / (z2 / alpha2 + z1 / alpha1);
 }
 
 // ----------------------------------------------------------------- WENO5-JS

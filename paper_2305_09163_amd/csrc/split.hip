@@ -508,7 +508,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
                 for (int v = 0; v < NV; v++) L[v] = lxy[v * g.vstride + c] + (Fz[v] - Fzn[v]) * idz;
                 divu = lxy[NV * g.vstride + c] + (Fzn[NV] - Fz[NV]) * idz;
             }
-            L[A] += win(1, A) * divu;
+            L[A] += alpha_source<T>(g, win(1, A), win(1, A - 1)) * divu;
             if (mode == 0) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) out[v * g.vstride + c] = L[v];

@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(kThreads) k_update(Grid g, const double *__res
         for (int v = 0; v < NV; v++) L[v] += (F[v * g.vstride + c] - F[v * g.vstride + c + s]) * g.inv_dx[d];
         divu += (F[NV * g.vstride + c + s] - F[NV * g.vstride + c]) * g.inv_dx[d];
     }
-    L[A] += w[A * g.vstride + c] * divu;
+    L[A] += alpha_source<double>(g, w[A * g.vstride + c], w[(A - 1) * g.vstride + c]) * divu;
     if (mode == 0) {
 #pragma unroll
         for (int v = 0; v < NV; v++) out[v * g.vstride + c] = L[v];

@@ -25,6 +25,7 @@ MFC_BC_EXTRAP, MFC_BC_PERIODIC = 0, 1
 MFC_FP64, MFC_FP32_MIXED = 0, 1
 MFC_RECON_WENO5, MFC_RECON_LEARNED = 0, 1
 MFC_KERNEL_FUSED, MFC_KERNEL_STAGED, MFC_KERNEL_SPLIT = 0, 1, 2
+MFC_MODEL_ALLAIRE, MFC_MODEL_KAPILA = 0, 1
 
 
 class MfcError(RuntimeError):
@@ -37,7 +38,8 @@ class mfc_grid_desc(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("num_fluids", ctypes.c_int), ("gamma", ctypes.c_double * 2),
                 ("pi_inf", ctypes.c_double * 2), ("bc", ctypes.c_int * 6), ("precision", ctypes.c_int),
-                ("recon", ctypes.c_int), ("weno_eps", ctypes.c_double), ("kernel", ctypes.c_int)]
+                ("recon", ctypes.c_int), ("weno_eps", ctypes.c_double), ("kernel", ctypes.c_int),
+                ("model", ctypes.c_int)]
 
 
 class mfc_batch_tune(ctypes.Structure):
@@ -140,7 +142,8 @@ def _ptr(t):
 
 def make_desc(spec, precision: int = MFC_FP64, recon: int = MFC_RECON_WENO5,
               kernel: int = MFC_KERNEL_FUSED) -> mfc_grid_desc:
-    """C descriptor from a GridSpec-like object (ndim, n, lo, hi, gamma, pi_inf, bc, weno_eps)."""
+    """C descriptor from a GridSpec-like object (ndim, n, lo, hi, gamma, pi_inf, bc, weno_eps and,
+    if present, model)."""
     d = mfc_grid_desc()
     d.ndim = spec.ndim
     for k in range(3):
@@ -156,6 +159,7 @@ def make_desc(spec, precision: int = MFC_FP64, recon: int = MFC_RECON_WENO5,
     d.recon = recon
     d.weno_eps = spec.weno_eps
     d.kernel = kernel
+    d.model = getattr(spec, "model", MFC_MODEL_ALLAIRE)
     return d
 
 

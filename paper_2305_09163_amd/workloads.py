@@ -41,6 +41,7 @@ class GridSpec:
     pi_inf: tuple = (WATER["pi_inf"], AIR["pi_inf"])
     bc: tuple = (0, 0, 0, 0, 0, 0)  # x-,x+,y-,y+,z-,z+: 0 extrapolation, 1 periodic
     weno_eps: float = 1.0e-6
+    model: int = 0                  # 0 Allaire five-equation model, 1 Kapila (with K div(u))
 
     def __post_init__(self):
         n = list(self.n) + [1] * (3 - len(self.n))

@@ -57,6 +57,7 @@ def desc(**kw):
     (dict(weno_eps=0.0), mfc.MFC_E_ARG),
     (dict(precision=9), mfc.MFC_E_ARG),
     (dict(kernel=9), mfc.MFC_E_ARG),
+    (dict(model=2), mfc.MFC_E_ARG),
 ])
 def test_init_rejects_invalid_descriptors(L, kw, code):
     h = ctypes.c_void_p(123)
@@ -102,6 +103,7 @@ def batch_descs(count=3, **kw):
     (dict(precision=mfc.MFC_FP64), mfc.MFC_E_ARG),   # mixed precisions in one batch
     (dict(num_fluids=3), mfc.MFC_E_UNSUPPORTED),
     (dict(recon=mfc.MFC_RECON_LEARNED), mfc.MFC_E_UNSUPPORTED),
+    (dict(model=-1), mfc.MFC_E_ARG),
     (dict(n=(2, 24, 1)), mfc.MFC_E_ARG),
     (dict(n=(40000, 24, 1)), mfc.MFC_E_ARG),
     (dict(gamma=(0.9, 1.4)), mfc.MFC_E_ARG),

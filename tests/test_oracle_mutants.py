@@ -9,7 +9,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mfc_oracle.c")
-PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_units.py", "test_oracle_scheme.py")]
+PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_units.py", "test_oracle_scheme.py",
+                                                  "test_oracle_kapila.py")]
 
 MUTANTS = {
     "weno ideal weights swapped": ("dplus[3] = {0.1, 0.6, 0.3}", "dplus[3] = {0.3, 0.6, 0.1}"),
@@ -23,8 +24,14 @@ MUTANTS = {
     "hllc star normal momentum": ("(m == dir ? rho * sS : rho * w[2 + m])", "(rho * w[2 + m])"),
     "hllc face alpha": ("alpha_face = w[nv - 1];", "alpha_face = wL[nv - 1];"),
     "hllc pressure on every momentum row": ("(m == dir ? p : 0.0)", "p"),
-    "rhs no alpha div(u) source": ("+= w[at(g, nv - 1, i, j, k)] * divu", "+= 0.0 * divu"),
-    "rhs source sign": ("+= w[at(g, nv - 1, i, j, k)] * divu", "-= w[at(g, nv - 1, i, j, k)] * divu"),
+    "rhs no alpha div(u) source": ("+= h * divu[at(g, 0, i, j, k)]", "+= 0.0 * h * divu[at(g, 0, i, j, k)]"),
+    "rhs source sign": ("+= h * divu[at(g, 0, i, j, k)]", "-= h * divu[at(g, 0, i, j, k)]"),
+    "kapila K as printed (rho1 c2^2)": ("(z2 / alpha2 + z1 / alpha1)", "(z2 / alpha2 + rho1 * c2sq / alpha1)"),
+    "kapila K sign": ("return (z2 - z1) / (z2", "return (z1 - z2) / (z2"),
+    "kapila volume fractions swapped": ("(z2 / alpha2 + z1 / alpha1)", "(z2 / alpha1 + z1 / alpha2)"),
+    "kapila phase sound speed without pi": ("g->gamma[0] * (p + g->pi_inf[0]) / rho1", "g->gamma[0] * p / rho1"),
+    "kapila source replaces alpha1": ("h += ora_kapila_K(g, wc);", "h = ora_kapila_K(g, wc);"),
+    "kapila source ignored": ("if (g->model == 1) {", "if (g->model == 7) {"),
     "rhs flux difference sign": ("(Ff[cell * nv + v] - Ff[(cell + 1) * nv + v]) * inv_dx", "(Ff[(cell + 1) * nv + v] - Ff[cell * nv + v]) * inv_dx"),
     "eos Pi without gamma": ("double h1 = g->gamma[0] * g->pi_inf[0]", "double h1 = g->pi_inf[0]"),
     "eos kinetic factor": ("ke += 0.5 * q[2 + m] * w[2 + m];", "ke += q[2 + m] * w[2 + m];"),
