@@ -53,8 +53,8 @@ def lib():
         path = os.environ.get("MFC_ORACLE_LIB")  # a deliberately broken build, for mutation tests
         if not path:
             path = _LIB_PATH
-            if not os.path.exists(path):
-                build(force=False)
+            if not os.path.exists(path) or os.path.getmtime(_SRC) > os.path.getmtime(path):
+                build(force=True)   # missing, or older than its source
         L = ctypes.CDLL(path)
         G = ctypes.POINTER(_Grid)
         sig = {
@@ -67,6 +67,7 @@ def lib():
             "ora_cons_to_prim": (ctypes.c_int, [G, _D, _D]),
             "ora_weno5": (None, [_D, ctypes.c_double, _D, _D, _D]),
             "ora_linear5": (None, [_D, _D, _D]),
+            "ora_weno3": (None, [_D, ctypes.c_double, _D, _D]),
             "ora_hllc": (ctypes.c_int, [G, ctypes.c_int, _D, _D, _D, _D]),
             "ora_fill_ghosts": (ctypes.c_int, [G, _D]),
             "ora_rhs": (ctypes.c_int, [G, _D, _D]),
@@ -85,7 +86,7 @@ def lib():
     return _lib
 
 
-RECON_WENO5, RECON_LINEAR, RECON_MASK = 0, 1, 2
+RECON_WENO5, RECON_LINEAR, RECON_MASK, RECON_WENO3, RECON_FIRST = 0, 1, 2, 3, 4
 MODEL_ALLAIRE, MODEL_KAPILA = 0, 1
 
 
@@ -152,6 +153,14 @@ def weno5(s, eps: float = 1e-6):
     a, b, dev = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     lib().ora_weno5(_ptr(s), eps, ctypes.byref(a), ctypes.byref(b), ctypes.byref(dev))
     return a.value, b.value, dev.value
+
+
+def weno3(s, eps: float = 1e-6):
+    """(value at x_{i+1/2}, value at x_{i-1/2}) from 3 cell averages."""
+    s = _arr(s)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().ora_weno3(_ptr(s), eps, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def linear5(s):
@@ -240,8 +249,9 @@ def rk3_step(spec, q, dt: float):
 
 def run(spec, q, nsteps: int, cfl: float = 0.0, dt: float = 0.0, recon: int = RECON_WENO5):
     """(q after nsteps steps, total time, status); CFL time step if cfl > 0.
-    recon RECON_LINEAR runs the linear fifth-order scheme everywhere."""
-    assert recon in (RECON_WENO5, RECON_LINEAR)
+    recon RECON_LINEAR runs the linear fifth-order scheme everywhere, RECON_WENO3
+    WENO3 and RECON_FIRST the first-order (cell-value) reconstruction."""
+    assert recon in (RECON_WENO5, RECON_LINEAR, RECON_WENO3, RECON_FIRST)
     q = _arr(q).copy()
     t = ctypes.c_double()
     st = lib().ora_run(ctypes.byref(grid(spec, recon)), _ptr(q), nsteps, cfl, dt, ctypes.byref(t))

@@ -60,7 +60,8 @@ typedef struct {
     double weno_eps;    /* WENO5-JS epsilon                               */
     int recon;          /* 0 WENO5 everywhere; 1 the linear fifth-order
                            stencil everywhere; 2 per (cell, direction) as
-                           `smooth` says                                   */
+                           `smooth` says; 3 WENO3 everywhere; 4 first
+                           order (cell values) everywhere                  */
     const unsigned char *smooth; /* recon 2: smooth[d * padded cells + c]
                            != 0 selects the linear stencil for every
                            variable of padded cell c along direction d    */
@@ -237,6 +238,37 @@ void ora_weno5(const double *s, double eps, double *at_plus, double *at_minus, d
     *at_plus = vp;
     *at_minus = vm;
     if (maxdev) *maxdev = dev;
+}
+
+/* WENO3-JS reconstruction (Sec. 3.2, the third-order variant: k = 2
+ * candidate stencils).  From s[0..2] = v_{i-1}, v_i, v_{i+1}:
+ *   candidates at x_{i+1/2}: (-v_{i-1} + 3 v_i)/2 on {i-1, i} and
+ *   (v_i + v_{i+1})/2 on {i, i+1}, ideal weights 1/3 and 2/3;
+ *   at x_{i-1/2} the mirror: (v_{i-1} + v_i)/2 and (3 v_i - v_{i+1})/2,
+ *   ideal weights 2/3 and 1/3;
+ *   smoothness indicators beta_0 = (v_i - v_{i-1})^2, beta_1 = (v_{i+1} - v_i)^2,
+ *   nonlinear weights alpha_r = d_r/(eps + beta_r)^2, omega_r = alpha_r/sum(alpha). */
+void ora_weno3(const double *s, double eps, double *at_plus, double *at_minus)
+{
+    double pp[2], pm[2], beta[2];
+    pp[0] = (-s[0] + 3.0 * s[1]) / 2.0;
+    pp[1] = (s[1] + s[2]) / 2.0;
+    pm[0] = (s[0] + s[1]) / 2.0;
+    pm[1] = (3.0 * s[1] - s[2]) / 2.0;
+    beta[0] = (s[1] - s[0]) * (s[1] - s[0]);
+    beta[1] = (s[2] - s[1]) * (s[2] - s[1]);
+    static const double dplus[2] = {1.0 / 3.0, 2.0 / 3.0};
+    static const double dminus[2] = {2.0 / 3.0, 1.0 / 3.0};
+    double ap[2], am[2], sp = 0.0, sm = 0.0;
+    for (int r = 0; r < 2; r++) {
+        double den = (eps + beta[r]) * (eps + beta[r]);
+        ap[r] = dplus[r] / den;
+        am[r] = dminus[r] / den;
+        sp += ap[r];
+        sm += am[r];
+    }
+    *at_plus = (ap[0] * pp[0] + ap[1] * pp[1]) / sp;
+    *at_minus = (am[0] * pm[0] + am[1] * pm[1]) / sm;
 }
 
 /* The linear fifth-order upwind reconstruction: the same candidates with
@@ -449,10 +481,15 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                             c[d] = cell;
                             lin = g->smooth[(int64_t)d * ora_padded_cells(g) + at(g, 0, c[0], c[1], c[2])] != 0;
                         }
-                        if (lin)
-                            ora_linear5(s, &rp[(cell + 1) * nv + v], &rm[(cell + 1) * nv + v]);
+                        double *pl = &rp[(cell + 1) * nv + v], *mi = &rm[(cell + 1) * nv + v];
+                        if (g->recon == 3)
+                            ora_weno3(&s[1], g->weno_eps, pl, mi);
+                        else if (g->recon == 4)
+                            *pl = *mi = s[2]; /* first order: the cell value at both faces */
+                        else if (lin)
+                            ora_linear5(s, pl, mi);
                         else
-                            ora_weno5(s, g->weno_eps, &rp[(cell + 1) * nv + v], &rm[(cell + 1) * nv + v], NULL);
+                            ora_weno5(s, g->weno_eps, pl, mi, NULL);
                     }
                 /* Riemann problems at faces f - 1/2, f = 0 .. n: left state
                  * from cell f-1 (its + face), right state from cell f */

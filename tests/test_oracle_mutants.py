@@ -10,7 +10,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mfc_oracle.c")
 PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_units.py", "test_oracle_scheme.py",
-                                                  "test_oracle_kapila.py")]
+                                                  "test_oracle_kapila.py", "test_oracle_order.py")]
 
 MUTANTS = {
     "weno ideal weights swapped": ("dplus[3] = {0.1, 0.6, 0.3}", "dplus[3] = {0.3, 0.6, 0.1}"),
@@ -32,6 +32,13 @@ MUTANTS = {
     "kapila phase sound speed without pi": ("g->gamma[0] * (p + g->pi_inf[0]) / rho1", "g->gamma[0] * p / rho1"),
     "kapila source replaces alpha1": ("h += ora_kapila_K(g, wc);", "h = ora_kapila_K(g, wc);"),
     "kapila source ignored": ("if (g->model == 1) {", "if (g->model == 7) {"),
+    "weno3 ideal weights swapped": ("dplus[2] = {1.0 / 3.0, 2.0 / 3.0}", "dplus[2] = {2.0 / 3.0, 1.0 / 3.0}"),
+    "weno3 candidate coefficient": ("pp[0] = (-s[0] + 3.0 * s[1]) / 2.0;", "pp[0] = (-s[0] + 2.0 * s[1]) / 2.0;"),
+    "weno3 smoothness indicator": ("beta[1] = (s[2] - s[1]) * (s[2] - s[1]);", "beta[1] = (s[2] - s[0]) * (s[2] - s[1]);"),
+    "weno3 mirror candidate": ("pm[1] = (3.0 * s[1] - s[2]) / 2.0;", "pm[1] = (3.0 * s[1] - s[0]) / 2.0;"),
+    "weno3 weight power 1": ("double den = (eps + beta[r]) * (eps + beta[r]);\n        ap[r] = dplus[r] / den;\n        am[r] = dminus[r] / den;\n        sp += ap[r];\n        sm += am[r];\n    }\n    *at_plus",
+                             "double den = (eps + beta[r]);\n        ap[r] = dplus[r] / den;\n        am[r] = dminus[r] / den;\n        sp += ap[r];\n        sm += am[r];\n    }\n    *at_plus"),
+    "first order from the neighbour": ("*pl = *mi = s[2];", "*pl = *mi = s[3];"),
     "rhs flux difference sign": ("(Ff[cell * nv + v] - Ff[(cell + 1) * nv + v]) * inv_dx", "(Ff[(cell + 1) * nv + v] - Ff[cell * nv + v]) * inv_dx"),
     "eos Pi without gamma": ("double h1 = g->gamma[0] * g->pi_inf[0]", "double h1 = g->pi_inf[0]"),
     "eos kinetic factor": ("ke += 0.5 * q[2 + m] * w[2 + m];", "ke += q[2 + m] * w[2 + m];"),
