@@ -14,7 +14,8 @@ PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_units.py", "test_o
 
 MUTANTS = {
     "weno ideal weights swapped": ("dplus[3] = {0.1, 0.6, 0.3}", "dplus[3] = {0.3, 0.6, 0.1}"),
-    "weno power 1 instead of 2": ("double den = (eps + beta[r]) * (eps + beta[r]);", "double den = (eps + beta[r]);"),
+    "weno power 1 instead of 2": ("double den = (eps + beta[r]) * (eps + beta[r]);\n        ap[r] = dplus[r] / den;\n        am[r] = dminus[r] / den;\n        sp += ap[r];\n        sm += am[r];\n    }\n    double vp",
+                                  "double den = (eps + beta[r]);\n        ap[r] = dplus[r] / den;\n        am[r] = dminus[r] / den;\n        sp += ap[r];\n        sm += am[r];\n    }\n    double vp"),
     "weno beta0 coefficient": ("(10.0 / 3.0) * dm1 * dm1 - (11.0 / 3.0) * dm1 * dm2", "(10.0 / 3.0) * dm1 * dm1 - (10.0 / 3.0) * dm1 * dm2"),
     "weno candidate coefficient": ("pp[1] = vi + (1.0 / 3.0) * d0", "pp[1] = vi + (1.0 / 6.0) * d0"),
     "weno mirror candidate": ("pm[2] = vi - (5.0 / 6.0) * d0 + (1.0 / 3.0) * d1", "pm[2] = vi - (5.0 / 6.0) * d0 + (1.0 / 6.0) * d1"),
