@@ -206,8 +206,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["bubble", "ensemble"], default="bubble",
                     help="bubble: the 3D bubble collapse (default); ensemble: 64 uneven 2D droplet-shock runs")
-    ap.add_argument("--recon", choices=["weno5", "learned"], default="weno5",
-                    help="learned: reconstruction routed by the trained indicator (weights from --weights)")
+    ap.add_argument("--recon", choices=["weno5", "learned", "weno3", "first"], default="weno5",
+                    help="learned: reconstruction routed by the trained indicator (weights from --weights); "
+                         "weno3 / first: the third- and first-order reconstructions")
     ap.add_argument("--model", choices=["allaire", "kapila"], default="allaire",
                     help="volume-fraction equation: Allaire (default) or Kapila (with the K div(u) source)")
     ap.add_argument("--tau", type=float, default=None,
@@ -249,9 +250,11 @@ def main():
             meta = os.path.splitext(args.weights)[0] + ".json"
             args.tau = json.load(open(meta))["tau"] if os.path.exists(meta) else 0.5
 
+    recon = {"weno5": mfc.MFC_RECON_WENO5, "learned": mfc.MFC_RECON_LEARNED, "weno3": mfc.MFC_RECON_WENO3,
+             "first": mfc.MFC_RECON_FIRST_ORDER}[args.recon]
+
     def make_solver():
-        s = mfc.Solver(spec, kernel=kernel, precision=precision,
-                       recon=mfc.MFC_RECON_LEARNED if learned else mfc.MFC_RECON_WENO5)
+        s = mfc.Solver(spec, kernel=kernel, precision=precision, recon=recon)
         if learned:
             s.set_indicator(weights, args.tau)
         return s
@@ -329,7 +332,7 @@ def main():
         out["config"]["tau"] = args.tau
     if roof_z:
         out["roofline_second_kernel"] = roof_z
-    if args.precision == "fp32" or learned:
+    if args.precision == "fp32" or args.recon != "weno5":
         out["error_vs_fp64_weno5"] = error_vs_reference(spec, w, make_solver, args.steps, mfc, weights, args.tau)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, w)

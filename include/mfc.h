@@ -59,7 +59,14 @@ enum {
 
 enum { MFC_BC_EXTRAP = 0, MFC_BC_PERIODIC = 1 };
 enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
-enum { MFC_RECON_WENO5 = 0, MFC_RECON_LEARNED = 1 };
+/* Reconstruction of the primitive variables at the faces (Sec. 3.2):
+ * WENO5-JS (the default), the learned routing between WENO5 and its linear
+ * fifth-order stencil (see mfc_set_indicator), WENO3-JS (two candidate
+ * stencils, ideal weights 1/3, 2/3 and their mirror, beta_r the squared
+ * one-sided differences, alpha_r = d_r/(eps + beta_r)^2), or first order
+ * (the cell value at both faces).  All of them read the same 3-cell ghost
+ * layers. */
+enum { MFC_RECON_WENO5 = 0, MFC_RECON_LEARNED = 1, MFC_RECON_WENO3 = 2, MFC_RECON_FIRST_ORDER = 3 };
 
 /* Volume-fraction equation (Sec. 2.1).  Allaire: d(alpha1)/dt + u . grad(alpha1)
  * = 0, i.e. the alpha1 row of eq. (fvmdis) carries alpha1_cell div(u).
@@ -93,9 +100,9 @@ typedef struct {
     int bc[6];           /* per face x-, x+, y-, y+, z-, z+: MFC_BC_*; periodic
                             must be set on both faces of a dimension               */
     int precision;       /* MFC_FP64 or MFC_FP32_MIXED                             */
-    int recon;           /* MFC_RECON_WENO5, or MFC_RECON_LEARNED (fused and split
-                            kernels; needs mfc_set_indicator before any
-                            right-hand side)                                       */
+    int recon;           /* MFC_RECON_*: WENO5, WENO3 or FIRST_ORDER (every kernel),
+                            or LEARNED (fused and split kernels; needs
+                            mfc_set_indicator before any right-hand side)          */
     double weno_eps;     /* WENO5-JS epsilon, > 0 (1e-6 in the paper's setting)    */
     int kernel;          /* MFC_KERNEL_*                                           */
     int model;           /* MFC_MODEL_ALLAIRE or MFC_MODEL_KAPILA                  */

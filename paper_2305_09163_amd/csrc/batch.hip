@@ -156,8 +156,15 @@ __device__ __forceinline__ bool load6(const Grid &g, const T *__restrict__ q, in
     return bad && outside <= 1;
 }
 
+// LDS of a tile (plane, face-value pairs, fluxes): the FP64 64 x 4 tile
+// (88 KB) fits one workgroup per CU, every other shape at least two
 template <int TX, int TY, class T>
-__global__ void __launch_bounds__(kBT, 2)
+constexpr int kBatchWaves =
+    sizeof(T) * (6 * Tile2<TX, TY, T>::PY * Tile2<TX, TY, T>::PX + 12 * Tile2<TX, TY, T>::NP + 7 * Tile2<TX, TY, T>::NF) >
+            80 * 1024 ? 1 : 2;
+
+template <int TX, int TY, class T>
+__global__ void __launch_bounds__(kBT, (kBatchWaves<TX, TY, T>))
     k_batch_stage(const RunDev<T> *__restrict__ runs, const int *__restrict__ item_run, const int *__restrict__ item_tile,
                   int nitems, const double *__restrict__ scal, int stage, int xcd, int *__restrict__ flag)
 {
@@ -558,6 +565,7 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
         g.h2 = d.gamma[1] * d.pi_inf[1] / (d.gamma[1] - 1.0);
         g.eps = d.weno_eps;
         set_kapila(g, d);
+        g.order = 5;
         b->grids.push_back(g);
         dxmin[r] = g.dxmin;
         b->cells += (int64_t)g.n[0] * g.n[1];

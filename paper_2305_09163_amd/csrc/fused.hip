@@ -66,15 +66,15 @@ __device__ __forceinline__ bool load_prim(const Grid &g, const T *__restrict__ q
     return bad && outside <= 1;
 }
 
-// Reconstruct one 5-cell stencil for all variables: WENO5, or the linear
-// stencil when lin is set.
-template <int NV, class T>
+// Reconstruct one 5-cell stencil for all variables: order ORDER (5 WENO5,
+// 3 WENO3, 1 first order), or the linear fifth-order stencil when lin is set.
+template <int ORDER, int NV, class T>
 __device__ __forceinline__ void recon_regs(const T (&zw)[5][NV], T eps, bool lin, T *plus, T *minus)
 {
 #pragma unroll
     for (int v = 0; v < NV; v++) {
         if (lin) linear5_pair<T>(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], plus[v], minus[v]);
-        else weno5_pair(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, plus[v], minus[v]);
+        else recon_pair<ORDER, T>(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, plus[v], minus[v]);
     }
 }
 
@@ -96,7 +96,7 @@ __device__ __forceinline__ bool route_regs(const mlp::Params &P, uint16_t *scrat
     return mlp::smooth_wave(P, scratch, f, logit_tau, lane);
 }
 
-template <int NDIM, class T, bool ROUTE>
+template <int NDIM, class T, bool ROUTE, int ORDER>
 __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
     k_fused(Grid g, const T *__restrict__ q, const T *q0, T *out, int mode, double dt,
             const double *__restrict__ dt_dev, int *__restrict__ flag, int lz, const float *__restrict__ mlpw,
@@ -145,14 +145,14 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
         T plus_prev[NV], mk[NV], dummy[NV];
         bool lin = false;
         if constexpr (ROUTE) lin = route_regs<NDIM, T>(s_mlp, scratch, zw, sqrt_eps, logit_tau, lane);
-        recon_regs<NV, T>(zw, eps, lin, plus_prev, dummy);
+        recon_regs<ORDER, NV, T>(zw, eps, lin, plus_prev, dummy);
 #pragma unroll
         for (int p = 0; p < 4; p++)
 #pragma unroll
             for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
         bad |= load_prim<NDIM, T>(g, q, cx, cy, z0 + 2, zw[4]);
         if constexpr (ROUTE) lin = route_regs<NDIM, T>(s_mlp, scratch, zw, sqrt_eps, logit_tau, lane);
-        recon_regs<NV, T>(zw, eps, lin, pk, mk);
+        recon_regs<ORDER, NV, T>(zw, eps, lin, pk, mk);
         bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0), T>(g, plus_prev, mk, Fz, Fz[NV]) && own;
     }
 
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
             for (int v = 0; v < NV; v++) wk[v] = zw[1][v];
             bool lin = false;
             if constexpr (ROUTE) lin = route_regs<NDIM, T>(s_mlp, scratch, zw, sqrt_eps, logit_tau, lane);
-            recon_regs<NV, T>(zw, eps, lin, pn, mn);
+            recon_regs<ORDER, NV, T>(zw, eps, lin, pn, mn);
             bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0), T>(g, pk, mn, Fzn, Fzn[NV]) && own;
 #pragma unroll
             for (int v = 0; v < NV; v++) pk[v] = pn[v];
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
                     for (int v = 0; v < NV; v++) {
                         const T *s = &s_plane[v][lj][c];
                         if (lin) linear5_pair<T>(s[0], s[1], s[2], s[3], s[4], s_pair[v][p], s_pair[NV + v][p]);
-                        else weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                        else recon_pair<ORDER, T>(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
                     }
                 }
             }
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     const T *s = &s_plane[v][lj][c];
-                    weno5_pair(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                    recon_pair<ORDER, T>(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
                 }
             }
         }
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
                                                 s_plane[v][r + 3][li], s_plane[v][r + 4][li], s_pair[v][p],
                                                 s_pair[NV + v][p]);
                             else
-                                weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                recon_pair<ORDER, T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
                                            s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, s_pair[v][p],
                                            s_pair[NV + v][p]);
                         }
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
                     const int li = c + NG;
 #pragma unroll
                     for (int v = 0; v < NV; v++)
-                        weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                        recon_pair<ORDER, T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
                                    s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, s_pair[v][p],
                                    s_pair[NV + v][p]);
                 }
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
     if (bad) atomicOr(flag, 1);
 }
 
-template <int NDIM, class T, bool ROUTE>
+template <int NDIM, class T, bool ROUTE, int ORDER>
 int rhs_fused(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s)
 {
     using S = Shape<NDIM>;
@@ -364,22 +364,22 @@ int rhs_fused(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
               NDIM == 3 ? (g.n[2] + kLZ - 1) / kLZ : 1);
     const T se = T(__builtin_sqrt(g.eps));
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_fused<NDIM, T, ROUTE>), grid, dim3(S::NT), 0, s, g, q, q0, out, mode, dt, dt_dev, h->flag, kLZ,
+    hipLaunchKernelGGL((k_fused<NDIM, T, ROUTE, ORDER>), grid, dim3(S::NT), 0, s, g, q, q0, out, mode, dt, dt_dev, h->flag, kLZ,
                        h->mlp, h->logit_tau, se);
     timing_end(h, s);
     return hip_status(hipGetLastError(), "fused right-hand side launch");
 }
 
-template <class T, bool ROUTE>
+template <class T, bool ROUTE, int ORDER>
 int rhs_fused_t(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt, const double *dt_dev,
                 hipStream_t s)
 {
     const T *a = (const T *)q, *b = (const T *)q0;
     T *o = (T *)out;
     switch (h->g.ndim) {
-    case 1: return rhs_fused<1, T, ROUTE>(h, a, b, o, mode, dt, dt_dev, s);
-    case 2: return rhs_fused<2, T, ROUTE>(h, a, b, o, mode, dt, dt_dev, s);
-    default: return rhs_fused<3, T, ROUTE>(h, a, b, o, mode, dt, dt_dev, s);
+    case 1: return rhs_fused<1, T, ROUTE, ORDER>(h, a, b, o, mode, dt, dt_dev, s);
+    case 2: return rhs_fused<2, T, ROUTE, ORDER>(h, a, b, o, mode, dt, dt_dev, s);
+    default: return rhs_fused<3, T, ROUTE, ORDER>(h, a, b, o, mode, dt, dt_dev, s);
     }
 }
 
@@ -390,11 +390,21 @@ int launch_rhs_fused(mfc_grid *h, const void *q, const void *q0, void *out, int 
 {
     const bool learned = h->desc.recon == MFC_RECON_LEARNED;
     if (learned && !h->mlp) return fail(MFC_E_ARG, "MFC_RECON_LEARNED needs mfc_set_indicator first");
-    if (h->desc.precision == MFC_FP32_MIXED)
-        return learned ? rhs_fused_t<float, true>(h, q, q0, out, mode, dt, dt_dev, s)
-                       : rhs_fused_t<float, false>(h, q, q0, out, mode, dt, dt_dev, s);
-    return learned ? rhs_fused_t<double, true>(h, q, q0, out, mode, dt, dt_dev, s)
-                   : rhs_fused_t<double, false>(h, q, q0, out, mode, dt, dt_dev, s);
+    const bool f32 = h->desc.precision == MFC_FP32_MIXED;
+    switch (h->desc.recon) {
+    case MFC_RECON_LEARNED:
+        return f32 ? rhs_fused_t<float, true, 5>(h, q, q0, out, mode, dt, dt_dev, s)
+                   : rhs_fused_t<double, true, 5>(h, q, q0, out, mode, dt, dt_dev, s);
+    case MFC_RECON_WENO3:
+        return f32 ? rhs_fused_t<float, false, 3>(h, q, q0, out, mode, dt, dt_dev, s)
+                   : rhs_fused_t<double, false, 3>(h, q, q0, out, mode, dt, dt_dev, s);
+    case MFC_RECON_FIRST_ORDER:
+        return f32 ? rhs_fused_t<float, false, 1>(h, q, q0, out, mode, dt, dt_dev, s)
+                   : rhs_fused_t<double, false, 1>(h, q, q0, out, mode, dt, dt_dev, s);
+    default:
+        return f32 ? rhs_fused_t<float, false, 5>(h, q, q0, out, mode, dt, dt_dev, s)
+                   : rhs_fused_t<double, false, 5>(h, q, q0, out, mode, dt, dt_dev, s);
+    }
 }
 
 }  // namespace mfc

@@ -246,7 +246,9 @@ int validate(const mfc_grid_desc *d)
     }
     if (!(d->weno_eps > 0.0)) return fail(MFC_E_ARG, "weno_eps must be > 0");
     if (d->precision != MFC_FP64 && d->precision != MFC_FP32_MIXED) return fail(MFC_E_ARG, "unknown precision");
-    if (d->recon != MFC_RECON_WENO5 && d->recon != MFC_RECON_LEARNED) return fail(MFC_E_ARG, "unknown recon");
+    if (d->recon != MFC_RECON_WENO5 && d->recon != MFC_RECON_LEARNED && d->recon != MFC_RECON_WENO3 &&
+        d->recon != MFC_RECON_FIRST_ORDER)
+        return fail(MFC_E_ARG, "unknown recon");
     if (d->model != MFC_MODEL_ALLAIRE && d->model != MFC_MODEL_KAPILA) return fail(MFC_E_ARG, "unknown model");
     if (d->kernel != MFC_KERNEL_FUSED && d->kernel != MFC_KERNEL_STAGED && d->kernel != MFC_KERNEL_SPLIT)
         return fail(MFC_E_ARG, "unknown kernel");
@@ -410,6 +412,7 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
     g.eps = desc->weno_eps;
     for (int f = 0; f < 6; f++) g.bc[f] = h->desc.bc[f];
     set_kapila(g, *desc);
+    g.order = desc->recon == MFC_RECON_WENO3 ? 3 : (desc->recon == MFC_RECON_FIRST_ORDER ? 1 : 5);
     h->cells_padded = g.vstride;
     h->cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
     if (hipGetDevice(&h->device) != hipSuccess ||

@@ -36,6 +36,7 @@ struct Grid {
     double g1, g2, h1, h2;
     double eps;       // WENO epsilon
     int bc[6];        // boundary kind per face (x-, x+, y-, y+, z-, z+): MFC_BC_*
+    int order;        // reconstruction of the staged path: 5 WENO5, 3 WENO3, 1 first order
     // Kapila alpha1 equation (kapila != 0): rho_k c_k^2 = zg[k] p + zp[k]
     int kapila;
     double zg[2], zp[2];  // gamma_k and gamma_k pi_k
@@ -218,6 +219,52 @@ __device__ __forceinline__ void weno5_pair(float vm2, float vm1, float v0, float
     const float r = rcp(6.0f * (sp * sm));
     plus = __builtin_fmaf(np, sm * r, v0);
     minus = __builtin_fmaf(nm, sp * r, v0);
+}
+
+// WENO3-JS from (vm1, v0, vp1): candidates at x_{i+1/2} v0 + a/2 and
+// v0 + c/2 (a = v0 - vm1, c = vp1 - v0) with ideal weights 1/3, 2/3; at
+// x_{i-1/2} v0 - a/2 and v0 - c/2 with 2/3, 1/3; beta_0 = a^2, beta_1 = c^2.
+// FP64 through common denominators (one reciprocal for both faces), FP32 in
+// the ratio form (terms in [0, 1]) as for WENO5.
+__device__ __forceinline__ void weno3_pair(double vm1, double v0, double vp1, double eps, double &plus,
+                                           double &minus)
+{
+    const double a = v0 - vm1, c = vp1 - v0;
+    const double e0 = __builtin_fma(a, a, eps), e1 = __builtin_fma(c, c, eps);
+    const double s0 = e0 * e0, s1 = e1 * e1;   // (eps + beta_r)^2
+    const double dp = __builtin_fma(2.0, s0, s1), dm = __builtin_fma(2.0, s1, s0);
+    const double r = rcp(2.0 * (dp * dm));
+    plus = __builtin_fma(__builtin_fma(2.0 * s0, c, s1 * a), dm * r, v0);
+    minus = __builtin_fma(-__builtin_fma(s0, c, 2.0 * s1 * a), dp * r, v0);
+}
+
+__device__ __forceinline__ void weno3_pair(float vm1, float v0, float vp1, float eps, float &plus, float &minus)
+{
+    const float a = v0 - vm1, c = vp1 - v0;
+    const float e0 = __builtin_fmaf(a, a, eps), e1 = __builtin_fmaf(c, c, eps);
+    const float emin = __builtin_fminf(e0, e1);
+    const float t0 = emin * rcp(e0), t1 = emin * rcp(e1);
+    const float m0 = t0 * t0, m1 = t1 * t1;    // proportional to 1/(eps + beta_r)^2
+    const float dp = __builtin_fmaf(2.0f, m1, m0), dm = __builtin_fmaf(2.0f, m0, m1);
+    plus = __builtin_fmaf(__builtin_fmaf(2.0f * m1, c, m0 * a), rcp(2.0f * dp), v0);
+    minus = __builtin_fmaf(-__builtin_fmaf(m1, c, 2.0f * m0 * a), rcp(2.0f * dm), v0);
+}
+
+// Both face values of a cell for reconstruction order ORDER from its 5-cell
+// stencil: 5 WENO5-JS, 3 WENO3-JS (inner three cells), 1 first order (the
+// cell value).
+template <int ORDER, class T>
+__device__ __forceinline__ void recon_pair(T vm2, T vm1, T v0, T vp1, T vp2, T eps, T &plus, T &minus)
+{
+    static_assert(ORDER == 5 || ORDER == 3 || ORDER == 1, "reconstruction order 5, 3 or 1");
+    if constexpr (ORDER == 5) {
+        weno5_pair(vm2, vm1, v0, vp1, vp2, eps, plus, minus);
+    } else if constexpr (ORDER == 3) {
+        weno3_pair(vm1, v0, vp1, eps, plus, minus);
+    } else {
+        plus = v0;
+        minus = v0;
+    }
 }
 
 // The linear fifth-order upwind reconstruction (the ideal-weight limit of

@@ -23,7 +23,8 @@
 // reconstruction (ROUTE = true): every (cell, direction) is first classified by
 // the learned indicator of mlp.h, a whole wavefront at a time, and a smooth
 // one takes the linear fifth-order stencil for every variable instead of
-// WENO5.
+// WENO5.  ORDER selects the reconstruction otherwise (5 WENO5, 3 WENO3,
+// 1 first order; the routed variant is always 5).
 #include <type_traits>
 
 #include "internal.h"
@@ -150,11 +151,12 @@ struct RouteLds {
 #ifndef MFC_XY_WAVES32
 #define MFC_XY_WAVES32 5
 #endif
-template <class T>
-constexpr int kXYWaves = sizeof(T) == 8 ? 3 : MFC_XY_WAVES32;
-
+// the routed variant's LDS (network, feature exchange) admits two workgroups per CU
 template <class T, bool ROUTE>
-__global__ void __launch_bounds__(NT, kXYWaves<T>)
+constexpr int kXYWaves = ROUTE ? 2 : (sizeof(T) == 8 ? 3 : MFC_XY_WAVES32);
+
+template <class T, bool ROUTE, int ORDER>
+__global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE>))
     k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag,
          const float *__restrict__ mlpw, float logit_tau, T sqrt_eps, double *__restrict__ smax_partial)
 {
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(NT, kXYWaves<T>)
                 for (int v = 0; v < NV; v++) {
                     const T *st = &s_plane[v][row + NG][c];
                     if (ROUTE && lin) linear5_pair<T>(st[0], st[1], st[2], st[3], st[4], wP[v], s_minus[v][p]);
-                    else weno5_pair(st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
+                    else recon_pair<ORDER, T>(st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
                 }
             }
         }
@@ -313,7 +315,7 @@ __global__ void __launch_bounds__(NT, kXYWaves<T>)
                         linear5_pair<T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
                                         s_plane[v][r + 3][li], s_plane[v][r + 4][li], wP[v], s_minus[v][p]);
                     else
-                        weno5_pair(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                        recon_pair<ORDER, T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
                                    s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, wP[v], s_minus[v][p]);
                 }
             }
@@ -401,7 +403,7 @@ constexpr int kRing = ROUTE ? MFC_Z_RING_ROUTE : MFC_Z_RING;
 static_assert(kRing<false> >= 1 && kRing<false> <= 4 && kRing<true> >= 1 && kRing<true> <= 4,
               "one to four planes in the ring");
 
-template <class T, bool ROUTE>
+template <class T, bool ROUTE, int ORDER>
 __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
     k_z(Grid g, const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ lxy, int mode, double dt,
         const double *__restrict__ dt_dev, int *__restrict__ flag, const float *__restrict__ mlpw, float logit_tau,
@@ -491,7 +493,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
         for (int v = 0; v < NV; v++) {
             const T w0 = win(0, v), w1 = win(1, v), w2 = win(2, v), w3 = win(3, v), w4 = win(4, v);
             if (ROUTE && lin) linear5_pair<T>(w0, w1, w2, w3, w4, pn[v], mn[v]);
-            else weno5_pair(w0, w1, w2, w3, w4, eps, pn[v], mn[v]);
+            else recon_pair<ORDER, T>(w0, w1, w2, w3, w4, eps, pn[v], mn[v]);
         }
         if (k >= z0 - 1) bad |= hllc<3, 2, T>(g, pk, mn, Fzn, Fzn[NV]);
 #pragma unroll
@@ -550,7 +552,7 @@ dim3 xy_grid(const Grid &g)
     return dim3((g.n[0] + TX - 1) / TX, (g.n[1] + TY - 1) / TY, (g.n[2] + kPlanesXY - 1) / kPlanesXY);
 }
 
-template <class T, bool ROUTE>
+template <class T, bool ROUTE, int ORDER>
 int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s,
               double cfl)
 {
@@ -561,11 +563,11 @@ int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
     const T se = T(__builtin_sqrt(g.eps));
     double *partial = cfl > 0.0 ? h->partial : nullptr;
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_xy<T, ROUTE>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se, partial);
+    hipLaunchKernelGGL((k_xy<T, ROUTE, ORDER>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se, partial);
     timing_end(h, s);
     if (partial) launch_step_begin(h, partial, (int)split_xy_blocks(g), cfl, 0.0, s);
     timing_begin(h, s, 1);
-    hipLaunchKernelGGL((k_z<T, ROUTE>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag, h->mlp,
+    hipLaunchKernelGGL((k_z<T, ROUTE, ORDER>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag, h->mlp,
                        h->logit_tau, se);
     timing_end(h, s, 1);
     return hip_status(hipGetLastError(), "split right-hand side launch");
@@ -587,11 +589,23 @@ int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int 
     if (learned && !h->mlp) return fail(MFC_E_ARG, "MFC_RECON_LEARNED needs mfc_set_indicator first");
     const float *fq = (const float *)q, *fq0 = (const float *)q0;
     const double *dq = (const double *)q, *dq0 = (const double *)q0;
-    if (h->desc.precision == MFC_FP32_MIXED)
-        return learned ? rhs_split<float, true>(h, fq, fq0, (float *)out, mode, dt, dt_dev, s, cfl)
-                       : rhs_split<float, false>(h, fq, fq0, (float *)out, mode, dt, dt_dev, s, cfl);
-    return learned ? rhs_split<double, true>(h, dq, dq0, (double *)out, mode, dt, dt_dev, s, cfl)
-                   : rhs_split<double, false>(h, dq, dq0, (double *)out, mode, dt, dt_dev, s, cfl);
+    float *fo = (float *)out;
+    double *dout = (double *)out;
+    const bool f32 = h->desc.precision == MFC_FP32_MIXED;
+    switch (h->desc.recon) {
+    case MFC_RECON_LEARNED:
+        return f32 ? rhs_split<float, true, 5>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                   : rhs_split<double, true, 5>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+    case MFC_RECON_WENO3:
+        return f32 ? rhs_split<float, false, 3>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                   : rhs_split<double, false, 3>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+    case MFC_RECON_FIRST_ORDER:
+        return f32 ? rhs_split<float, false, 1>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                   : rhs_split<double, false, 1>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+    default:
+        return f32 ? rhs_split<float, false, 5>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                   : rhs_split<double, false, 5>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+    }
 }
 
 }  // namespace mfc

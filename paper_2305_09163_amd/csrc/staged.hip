@@ -68,7 +68,11 @@ __global__ void __launch_bounds__(kThreads) k_recon(Grid g, const double *__rest
     for (int v = 0; v < NV; v++) {
         const double *x = w + v * g.vstride + c;
         double plus, minus;
-        weno5_pair(x[-2 * s], x[-s], x[0], x[s], x[2 * s], g.eps, plus, minus);
+        switch (g.order) {
+        case 3: recon_pair<3, double>(x[-2 * s], x[-s], x[0], x[s], x[2 * s], g.eps, plus, minus); break;
+        case 1: recon_pair<1, double>(x[-2 * s], x[-s], x[0], x[s], x[2 * s], g.eps, plus, minus); break;
+        default: recon_pair<5, double>(x[-2 * s], x[-s], x[0], x[s], x[2 * s], g.eps, plus, minus);
+        }
         rp[v * g.vstride + c] = plus;
         rm[v * g.vstride + c] = minus;
     }

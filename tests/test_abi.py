@@ -58,6 +58,7 @@ def desc(**kw):
     (dict(precision=9), mfc.MFC_E_ARG),
     (dict(kernel=9), mfc.MFC_E_ARG),
     (dict(model=2), mfc.MFC_E_ARG),
+    (dict(recon=9), mfc.MFC_E_ARG),
 ])
 def test_init_rejects_invalid_descriptors(L, kw, code):
     h = ctypes.c_void_p(123)
@@ -104,6 +105,7 @@ def batch_descs(count=3, **kw):
     (dict(num_fluids=3), mfc.MFC_E_UNSUPPORTED),
     (dict(recon=mfc.MFC_RECON_LEARNED), mfc.MFC_E_UNSUPPORTED),
     (dict(model=-1), mfc.MFC_E_ARG),
+    (dict(recon=mfc.MFC_RECON_WENO3), mfc.MFC_E_UNSUPPORTED),
     (dict(n=(2, 24, 1)), mfc.MFC_E_ARG),
     (dict(n=(40000, 24, 1)), mfc.MFC_E_ARG),
     (dict(gamma=(0.9, 1.4)), mfc.MFC_E_ARG),

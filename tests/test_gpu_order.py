@@ -1,0 +1,127 @@
+"""The lower-order reconstructions of Sec. 3.2 on the GPU (WENO3-JS and the
+first-order cell values) against the oracle's: right-hand side and one step
+on 1D/2D/3D workloads for every kernel, 200 steps of the shock tube, 20
+steps of the 3D bubble on the split path, and the FP32 form's error."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import acoustic_floor, rel_l1, rel_linf, rhs_err
+from paper_2305_09163_amd import mfc
+from paper_2305_09163_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+KERNELS = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}
+RECON = {"weno3": (mfc.MFC_RECON_WENO3, oracle.RECON_WENO3), "first": (mfc.MFC_RECON_FIRST_ORDER, oracle.RECON_FIRST)}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+CASES = {
+    "shock_tube_400": lambda: W.shock_tube_1d(400),
+    "droplet_2d_45": lambda: W.droplet_shock_2d(45, W.SEED + 11),
+    "bubble_3d_17x15x17": lambda: W.bubble_collapse_3d(n=(17, 15, 17)),
+    "periodic_3d_13": lambda: W.random_smooth_periodic(3, 13),
+}
+PAIRS = [(name, k, r) for name, make in CASES.items() for k in sorted(KERNELS) for r in sorted(RECON)
+         if k != "split" or make()[0].ndim == 3]
+
+
+@pytest.mark.parametrize("name,kernel,recon", PAIRS)
+def test_rhs_and_step(name, kernel, recon):
+    spec, w = CASES[name]()
+    rg, ro_kind = RECON[recon]
+    say(f"[{recon}] {name} kernel={kernel}")
+    s = mfc.Solver(spec, kernel=KERNELS[kernel], recon=rg)
+    q = s.state_from_prim(w)
+    s.fill_ghosts(q)
+    r = s.rhs(q).cpu().numpy()
+    s.check()
+    qo = oracle.fill_ghosts(spec, oracle.prim_to_cons_field(spec, w))
+    ro, st = oracle.rhs(spec, qo, recon=ro_kind)
+    assert st == oracle.OK
+    err = rhs_err(r, ro, qo, spec)
+    # it is not WENO5: the GPU result is far closer to this reconstruction's
+    # oracle than to the WENO5 one (the piecewise-constant shock tube at t = 0
+    # cannot tell them apart: every scheme takes the smooth side of the jump)
+    if name != "shock_tube_400":
+        r5, _ = oracle.rhs(spec, qo)
+        assert rhs_err(r, r5, qo, spec).max() > 100 * max(err.max(), 1e-15)
+    q1 = s.state_from_prim(w)
+    s.step(q1, cfl=0.3)
+    s.check()
+    qn, _, st = oracle.run(spec, oracle.prim_to_cons_field(spec, w), 1, cfl=0.3, recon=ro_kind)
+    assert st == oracle.OK
+    e1 = rel_linf(q1.cpu().numpy(), qn, spec, floor_mom=acoustic_floor(spec, qo))
+    say(f"    rhs err {err.max():.2e}, one-step rel Linf {e1.max():.2e}")
+    assert err.max() <= 1e-12 and e1.max() <= 1e-12
+
+
+@pytest.mark.parametrize("recon", sorted(RECON))
+def test_shock_tube_200_steps(recon):
+    spec, w = W.shock_tube_1d(400)
+    rg, ro_kind = RECON[recon]
+    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_FUSED, recon=rg)
+    q = s.state_from_prim(w)
+    s.run(q, 200, cfl=0.4)
+    t, _ = s.time()
+    s.check()
+    qo, to, st = oracle.run(spec, oracle.prim_to_cons_field(spec, w), 200, cfl=0.4, recon=ro_kind)
+    assert st == oracle.OK
+    assert t == pytest.approx(to, rel=1e-11)
+    err = rel_l1(q.cpu().numpy(), qo, spec)
+    say(f"[{recon} 200 steps] shock tube rel L1 {err}")
+    assert err.max() <= 1e-10
+
+
+@pytest.mark.parametrize("recon", sorted(RECON))
+def test_bubble_20_steps_split(recon):
+    spec, w = W.bubble_collapse_3d(n=32)
+    rg, ro_kind = RECON[recon]
+    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_SPLIT, recon=rg)
+    q = s.state_from_prim(w)
+    s.run(q, 20, cfl=0.3)
+    s.check()
+    qi = oracle.prim_to_cons_field(spec, w)
+    qo, _, st = oracle.run(spec, qi, 20, cfl=0.3, recon=ro_kind)
+    assert st == oracle.OK
+    err = rel_l1(q.cpu().numpy(), qo, spec, floor_mom=acoustic_floor(spec, qi))
+    say(f"[{recon} 20 steps] bubble 32^3 rel L1 {err}")
+    assert err.max() <= 1e-10
+
+
+@pytest.mark.parametrize("kernel", ["fused", "split"])
+@pytest.mark.parametrize("recon", sorted(RECON))
+def test_fp32_one_step(recon, kernel):
+    spec, w = W.bubble_collapse_3d(n=(37, 21, 19))
+    rg, ro_kind = RECON[recon]
+    s = mfc.Solver(spec, precision=mfc.MFC_FP32_MIXED, kernel=KERNELS[kernel], recon=rg)
+    q = s.state_from_prim(w)
+    s.step(q, cfl=0.3)
+    s.check()
+    qi = oracle.prim_to_cons_field(spec, w)
+    qo, _, st = oracle.run(spec, qi, 1, cfl=0.3, recon=ro_kind)
+    assert st == oracle.OK
+    got = q.double().cpu().numpy()
+    I = spec.interior[1:]
+    rho_err = np.abs((got[0] + got[1])[I] - (qo[0] + qo[1])[I]).sum() / np.abs((qo[0] + qo[1])[I]).sum()
+    linf = rel_linf(got, qo, spec, floor_mom=acoustic_floor(spec, qi))
+    say(f"[{recon} fp32 1 step] {kernel}: rho L1 {rho_err:.2e}, rel Linf {linf.max():.2e}")
+    assert rho_err <= 1e-6 and linf.max() <= 2e-4
+
+
+@pytest.mark.parametrize("recon", sorted(RECON))
+def test_uniform_state_zero_rhs(recon):
+    import torch
+    spec, w = W.uniform_state(3, 19)
+    for kernel in sorted(KERNELS):
+        s = mfc.Solver(spec, kernel=KERNELS[kernel], recon=RECON[recon][0])
+        q = s.state_from_prim(w)
+        s.fill_ghosts(q)
+        r = s.rhs(q)
+        s.check()
+        assert torch.count_nonzero(r[(slice(None),) + spec.interior[1:]]).item() == 0, kernel
