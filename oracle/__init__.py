@@ -37,14 +37,14 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+_D = ctypes.POINTER(ctypes.c_double)
+
+
 class _Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3),
                 ("gamma", ctypes.c_double * 2), ("pi_inf", ctypes.c_double * 2), ("bc", ctypes.c_int * 6),
                 ("weno_eps", ctypes.c_double), ("recon", ctypes.c_int),
-                ("smooth", ctypes.POINTER(ctypes.c_ubyte)), ("model", ctypes.c_int)]
-
-
-_D = ctypes.POINTER(ctypes.c_double)
+                ("smooth", ctypes.POINTER(ctypes.c_ubyte)), ("model", ctypes.c_int), ("faces", _D * 3)]
 
 
 def lib():
@@ -68,6 +68,8 @@ def lib():
             "ora_weno5": (None, [_D, ctypes.c_double, _D, _D, _D]),
             "ora_linear5": (None, [_D, _D, _D]),
             "ora_weno3": (None, [_D, ctypes.c_double, _D, _D]),
+            "ora_weno5_nonuniform_cell": (None, [_D, _D, ctypes.c_double, _D, _D]),
+            "ora_weno5_nonuniform_betas": (None, [_D, _D, _D]),
             "ora_hllc": (ctypes.c_int, [G, ctypes.c_int, _D, _D, _D, _D]),
             "ora_fill_ghosts": (ctypes.c_int, [G, _D]),
             "ora_rhs": (ctypes.c_int, [G, _D, _D]),
@@ -109,6 +111,13 @@ def grid(spec, recon: int = RECON_WENO5, smooth=None) -> _Grid:
         g.bc[f] = spec.bc[f]
     g.weno_eps = spec.weno_eps
     g.model = getattr(spec, "model", MODEL_ALLAIRE)
+    g._keep = []
+    for d in range(3):
+        f = spec.face_coords(d) if hasattr(spec, "face_coords") else None
+        if f is not None:
+            assert f.shape == (spec.n[d] + 1,) and np.all(np.diff(f) > 0)
+            g._keep.append(f)
+            g.faces[d] = f.ctypes.data_as(_D)
     return g
 
 
@@ -161,6 +170,22 @@ def weno3(s, eps: float = 1e-6):
     a, b = ctypes.c_double(), ctypes.c_double()
     lib().ora_weno3(_ptr(s), eps, ctypes.byref(a), ctypes.byref(b))
     return a.value, b.value
+
+
+def weno5_nonuniform(widths, s, eps: float = 1e-6):
+    """(value at x_{i+1/2}, value at x_{i-1/2}) of cell i from the widths and
+    averages of cells i-2 .. i+2 (non-uniform WENO5)."""
+    widths, s = _arr(widths), _arr(s)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().ora_weno5_nonuniform_cell(_ptr(widths), _ptr(s), eps, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def weno5_nonuniform_betas(widths, s):
+    widths, s = _arr(widths), _arr(s)
+    out = np.empty(3)
+    lib().ora_weno5_nonuniform_betas(_ptr(widths), _ptr(s), _ptr(out))
+    return out
 
 
 def linear5(s):

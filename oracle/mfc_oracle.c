@@ -67,6 +67,9 @@ typedef struct {
                            variable of padded cell c along direction d    */
     int model;          /* 0 Allaire (alpha1 equation without K div(u));
                            1 Kapila (with K div(u))                       */
+    const double *faces[3]; /* non-uniform grid: faces[d][0 .. n_d] are the
+                           n_d + 1 interior face coordinates along d (NULL:
+                           uniform cells of width dx[d])                   */
 } ora_grid;
 
 int ora_nvar(int ndim) { return 4 + ndim; }
@@ -83,6 +86,19 @@ static int64_t at(const ora_grid *g, int v, int i, int j, int k)
 }
 
 int64_t ora_padded_cells(const ora_grid *g) { return pad(g, 0) * pad(g, 1) * pad(g, 2); }
+
+/* Width of cell i (-NG <= i < n + NG) along dimension d.  Ghost cells take
+ * the width of the interior cell whose value the ghost fill copies there:
+ * mirrored for extrapolation (cell -1 <- 0, -2 <- 1, n <- n-1, ...),
+ * one period away for periodic boundaries. */
+double ora_cell_width(const ora_grid *g, int d, int i)
+{
+    if (!g->faces[d]) return g->dx[d];
+    int n = g->n[d];
+    if (i < 0) i = g->bc[2 * d] == 1 ? i + n : -1 - i;
+    else if (i >= n) i = g->bc[2 * d + 1] == 1 ? i - n : 2 * n - 1 - i;
+    return g->faces[d][i + 1] - g->faces[d][i];
+}
 
 /* ---------------------------------------------------------------------- */
 /* Equation of state (Sec. 2.1, eq. soe)                                    */
@@ -238,6 +254,165 @@ void ora_weno5(const double *s, double eps, double *at_plus, double *at_minus, d
     *at_plus = vp;
     *at_minus = vm;
     if (maxdev) *maxdev = dev;
+}
+
+/* WENO5 on non-uniform cells (Sec. 3.2 with cell widths Delta x_i).  For
+ * cell i the candidate polynomial p_r (degree 2) is the one whose averages
+ * over the three cells of stencil r ({i-2+r .. i+r}) equal the data; the
+ * face values are p_r(x_{i+1/2}) and p_r(x_{i-1/2}); the smoothness
+ * indicator is beta_r = sum_{l=1,2} Delta x_i^{2l-1} int_{I_i} (d^l p_r/dx^l)^2,
+ * which for p_r = a0 + a1 xi + a2 xi^2, xi = (x - x_i)/Delta x_i, is
+ * a1^2 + (13/3) a2^2; the ideal weights d_r are those for which
+ * sum_r d_r p_r(face) equals the face value of the degree-4 polynomial
+ * whose averages over all five cells equal the data.  Everything is linear
+ * in the data: the coefficients below are computed once per cell from the
+ * widths by solving the cell-average systems in xi. */
+typedef struct {
+    double plus[3][3], minus[3][3]; /* p_r(x_{i+1/2}), p_r(x_{i-1/2}) on stencil r's cells */
+    double a1[3][3], a2[3][3];      /* a1, a2 of p_r on stencil r's cells                */
+    double dplus[3], dminus[3];     /* ideal weights                                    */
+} ora_weno_coef;
+
+/* Solve the m x m system A x = b (m <= 5) by Gaussian elimination with
+ * partial pivoting; A and b are overwritten. */
+static void solve_small(int m, double A[5][5], double *b, double *x)
+{
+    for (int c = 0; c < m; c++) {
+        int piv = c;
+        for (int r = c + 1; r < m; r++)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        for (int k = 0; k < m; k++) {
+            double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t;
+        }
+        double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        for (int r = c + 1; r < m; r++) {
+            double f = A[r][c] / A[c][c];
+            for (int k = c; k < m; k++) A[r][k] -= f * A[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = m - 1; r >= 0; r--) {
+        double acc = b[r];
+        for (int k = r + 1; k < m; k++) acc -= A[r][k] * x[k];
+        x[r] = acc / A[r][r];
+    }
+}
+
+/* Polynomial coefficients (in xi about cell i, scaled by h_i) of the degree
+ * m-1 polynomial whose averages over the m consecutive cells starting at
+ * cell offset `first` (relative to i) equal e_j: coef[j][k] is the xi^k
+ * coefficient for unit data on the j-th of those cells.  w[t] is the width
+ * of cell i - 2 + t, t = 0..4. */
+static void average_inverse(const double *w, int first, int m, double coef[5][5])
+{
+    /* cell edges in xi: cell i spans [-1/2, 1/2] */
+    double edge[6];
+    edge[2] = -0.5;
+    for (int t = 2; t < 5; t++) edge[t + 1] = edge[t] + w[t] / w[2];
+    for (int t = 2; t > 0; t--) edge[t - 1] = edge[t] - w[t - 1] / w[2];
+    for (int j = 0; j < m; j++) {
+        double A[5][5], b[5], x[5];
+        for (int r = 0; r < m; r++) {
+            int t = first + 2 + r;          /* cell index within w[] */
+            double lo = edge[t], hi = edge[t + 1];
+            for (int k = 0; k < m; k++)
+                A[r][k] = (pow(hi, k + 1) - pow(lo, k + 1)) / ((k + 1) * (hi - lo));
+            b[r] = r == j ? 1.0 : 0.0;
+        }
+        solve_small(m, A, b, x);
+        for (int k = 0; k < m; k++) coef[j][k] = x[k];
+    }
+}
+
+static double poly_at(const double *c, int m, double xi)
+{
+    double v = 0.0;
+    for (int k = m - 1; k >= 0; k--) v = v * xi + c[k];
+    return v;
+}
+
+/* Coefficients for cell i from the widths w[0..4] of cells i-2 .. i+2. */
+void ora_weno_coef_nonuniform(const double *w, ora_weno_coef *cf)
+{
+    double q5[5][5], q3[5][5];
+    average_inverse(w, -2, 5, q5);
+    double qplus[5], qminus[5];
+    for (int j = 0; j < 5; j++) {
+        qplus[j] = poly_at(q5[j], 5, 0.5);
+        qminus[j] = poly_at(q5[j], 5, -0.5);
+    }
+    for (int r = 0; r < 3; r++) {
+        average_inverse(w, r - 2, 3, q3);
+        for (int j = 0; j < 3; j++) {
+            cf->plus[r][j] = poly_at(q3[j], 3, 0.5);
+            cf->minus[r][j] = poly_at(q3[j], 3, -0.5);
+            cf->a1[r][j] = q3[j][1];
+            cf->a2[r][j] = q3[j][2];
+        }
+    }
+    /* sum_r d_r p_r = q on every datum: the outermost cells appear in one
+     * stencil each (r = 0 holds cell i-2, r = 2 holds cell i+2), and the
+     * weights sum to one */
+    cf->dplus[0] = qplus[0] / cf->plus[0][0];
+    cf->dplus[2] = qplus[4] / cf->plus[2][2];
+    cf->dplus[1] = 1.0 - cf->dplus[0] - cf->dplus[2];
+    cf->dminus[0] = qminus[0] / cf->minus[0][0];
+    cf->dminus[2] = qminus[4] / cf->minus[2][2];
+    cf->dminus[1] = 1.0 - cf->dminus[0] - cf->dminus[2];
+}
+
+/* Smoothness indicator of stencil r for the values s[0..4]. */
+static double beta_nonuniform(const ora_weno_coef *cf, int r, const double *s)
+{
+    double a1 = 0.0, a2 = 0.0;
+    for (int j = 0; j < 3; j++) {
+        a1 += cf->a1[r][j] * s[r + j];
+        a2 += cf->a2[r][j] * s[r + j];
+    }
+    return a1 * a1 + (13.0 / 3.0) * a2 * a2;
+}
+
+/* Non-uniform WENO5 of the five values s[0..4] (cells i-2 .. i+2). */
+void ora_weno5_nonuniform(const ora_weno_coef *cf, const double *s, double eps, double *at_plus,
+                          double *at_minus)
+{
+    double ap[3], am[3], pp[3], pm[3], sp = 0.0, sm = 0.0;
+    for (int r = 0; r < 3; r++) {
+        pp[r] = pm[r] = 0.0;
+        for (int j = 0; j < 3; j++) {
+            pp[r] += cf->plus[r][j] * s[r + j];
+            pm[r] += cf->minus[r][j] * s[r + j];
+        }
+        double beta = beta_nonuniform(cf, r, s);
+        double den = (eps + beta) * (eps + beta);
+        ap[r] = cf->dplus[r] / den;
+        am[r] = cf->dminus[r] / den;
+        sp += ap[r];
+        sm += am[r];
+    }
+    double vp = 0.0, vm = 0.0;
+    for (int r = 0; r < 3; r++) {
+        vp += ap[r] / sp * pp[r];
+        vm += am[r] / sm * pm[r];
+    }
+    *at_plus = vp;
+    *at_minus = vm;
+}
+
+/* One cell's non-uniform WENO5 from the widths w[0..4] and values s[0..4]
+ * of cells i-2 .. i+2, and its three smoothness indicators (test access). */
+void ora_weno5_nonuniform_cell(const double *w, const double *s, double eps, double *at_plus, double *at_minus)
+{
+    ora_weno_coef cf;
+    ora_weno_coef_nonuniform(w, &cf);
+    ora_weno5_nonuniform(&cf, s, eps, at_plus, at_minus);
+}
+
+void ora_weno5_nonuniform_betas(const double *w, const double *s, double *beta)
+{
+    ora_weno_coef cf;
+    ora_weno_coef_nonuniform(w, &cf);
+    for (int r = 0; r < 3; r++) beta[r] = beta_nonuniform(&cf, r, s);
 }
 
 /* WENO3-JS reconstruction (Sec. 3.2, the third-order variant: k = 2
@@ -462,7 +637,24 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
         int n = g->n[d];
         int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
         int n1 = o1 < nd ? g->n[o1] : 1, n2 = o2 < nd ? g->n[o2] : 1;
-        double inv_dx = 1.0 / g->dx[d];
+        /* non-uniform cells: WENO5 coefficients of every cell -1 .. n along d */
+        ora_weno_coef *cf = NULL;
+        if (g->faces[d]) {
+            if (g->recon != 0 && g->recon != 4) {
+                status = ORA_E_ARG;   /* non-uniform cells take WENO5 or first order */
+                break;
+            }
+            cf = malloc(sizeof(ora_weno_coef) * (n + 2));
+            if (!cf) {
+                status = ORA_E_NOMEM;
+                break;
+            }
+            for (int cell = -1; cell <= n; cell++) {
+                double wd[5];
+                for (int t = 0; t < 5; t++) wd[t] = ora_cell_width(g, d, cell - 2 + t);
+                ora_weno_coef_nonuniform(wd, &cf[cell + 1]);
+            }
+        }
         for (int b = 0; b < n2; b++)
             for (int a = 0; a < n1; a++) {
                 int c[3];
@@ -482,7 +674,9 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                             lin = g->smooth[(int64_t)d * ora_padded_cells(g) + at(g, 0, c[0], c[1], c[2])] != 0;
                         }
                         double *pl = &rp[(cell + 1) * nv + v], *mi = &rm[(cell + 1) * nv + v];
-                        if (g->recon == 3)
+                        if (cf && g->recon == 0)
+                            ora_weno5_nonuniform(&cf[cell + 1], s, g->weno_eps, pl, mi);
+                        else if (g->recon == 3)
                             ora_weno3(&s[1], g->weno_eps, pl, mi);
                         else if (g->recon == 4)
                             *pl = *mi = s[2]; /* first order: the cell value at both faces */
@@ -499,12 +693,14 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                 }
                 /* flux differences and the divergence of the face velocity */
                 for (int cell = 0; cell < n; cell++) {
+                    double inv_dx = 1.0 / ora_cell_width(g, d, cell);
                     c[d] = cell;
                     for (int v = 0; v < nv; v++)
                         rhs[at(g, v, c[0], c[1], c[2])] += (Ff[cell * nv + v] - Ff[(cell + 1) * nv + v]) * inv_dx;
                     divu[at(g, 0, c[0], c[1], c[2])] += (uf[cell + 1] - uf[cell]) * inv_dx;
                 }
             }
+        free(cf);
     }
     /* non-conservative source: -h div(u) with h = -alpha1 (Allaire) or
      * h = -(alpha1 + K) (Kapila) on the alpha1 row */
@@ -596,8 +792,37 @@ int ora_rk3_step(const ora_grid *g, double *q, double dt)
     return status;
 }
 
-/* nsteps steps; dt = cfl * min_d dx_d / smax(q^n) if cfl > 0, else dt_fixed.
- * *t_out receives the total time advanced. */
+/* The CFL step on non-uniform cells: cfl times the smallest, over interior
+ * cells and dimensions, of Delta x_d(cell) / (|u_d| + c). */
+int ora_cfl_dt_nonuniform(const ora_grid *g, const double *q, double cfl, double *dt)
+{
+    int nd = g->ndim, nv = 4 + nd, status = ORA_OK;
+    double m = INFINITY;
+    for (int k = 0; k < g->n[2]; k++)
+        for (int j = 0; j < g->n[1]; j++)
+            for (int i = 0; i < g->n[0]; i++) {
+                double qc[MAXV], wc[MAXV];
+                for (int v = 0; v < nv; v++) qc[v] = q[at(g, v, i, j, k)];
+                if (ora_cons_to_prim(g, qc, wc) != ORA_OK) status = ORA_E_NONPHYSICAL;
+                double c = sqrt(ora_sound_speed2(g, wc[0] + wc[1], wc[2 + nd], wc[nv - 1]));
+                int idx[3] = {i, j, k};
+                for (int d = 0; d < nd; d++) {
+                    double r = ora_cell_width(g, d, idx[d]) / (fabs(wc[2 + d]) + c);
+                    if (r < m) m = r;
+                }
+            }
+    *dt = cfl * m;
+    return status;
+}
+
+static int nonuniform(const ora_grid *g)
+{
+    return g->faces[0] || g->faces[1] || g->faces[2];
+}
+
+/* nsteps steps; dt = cfl * min_d dx_d / smax(q^n) if cfl > 0 (on
+ * non-uniform cells cfl * min over cells and d of Delta x_d/(|u_d| + c)),
+ * else dt_fixed.  *t_out receives the total time advanced. */
 int ora_run(const ora_grid *g, double *q, int nsteps, double cfl, double dt_fixed, double *t_out)
 {
     double t = 0.0, dxmin = g->dx[0];
@@ -606,7 +831,10 @@ int ora_run(const ora_grid *g, double *q, int nsteps, double cfl, double dt_fixe
     int status = ORA_OK;
     for (int s = 0; s < nsteps && status == ORA_OK; s++) {
         double dt = dt_fixed;
-        if (cfl > 0.0) {
+        if (cfl > 0.0 && nonuniform(g)) {
+            status = ora_cfl_dt_nonuniform(g, q, cfl, &dt);
+            if (status != ORA_OK) break;
+        } else if (cfl > 0.0) {
             double smax;
             status = ora_max_wavespeed(g, q, &smax);
             if (status != ORA_OK) break;

@@ -42,6 +42,8 @@ class GridSpec:
     bc: tuple = (0, 0, 0, 0, 0, 0)  # x-,x+,y-,y+,z-,z+: 0 extrapolation, 1 periodic
     weno_eps: float = 1.0e-6
     model: int = 0                  # 0 Allaire five-equation model, 1 Kapila (with K div(u))
+    faces: tuple = None             # non-uniform grid: per dimension the n_d + 1 interior face
+                                    # coordinates (None for a uniform dimension), or None
 
     def __post_init__(self):
         n = list(self.n) + [1] * (3 - len(self.n))
@@ -78,12 +80,25 @@ class GridSpec:
     def cells(self) -> int:
         return self.n[0] * self.n[1] * self.n[2]
 
+    def face_coords(self, d: int):
+        """Interior face coordinates along d of a non-uniform dimension, else None."""
+        if self.faces is None or d >= self.ndim or self.faces[d] is None:
+            return None
+        return np.ascontiguousarray(self.faces[d], dtype=np.float64)
+
     def centres(self, d: int) -> np.ndarray:
-        """Cell-centre coordinates along dimension d, ghost cells included."""
+        """Cell-centre coordinates along dimension d, ghost cells included
+        (ghost cells of a non-uniform dimension continue its end widths)."""
         if d >= self.ndim:
             return np.array([0.5 * (self.lo[d] + self.hi[d])])
-        i = np.arange(-NG, self.n[d] + NG)
-        return self.lo[d] + (i + 0.5) * self.dx[d]
+        f = self.face_coords(d)
+        if f is None:
+            i = np.arange(-NG, self.n[d] + NG)
+            return self.lo[d] + (i + 0.5) * self.dx[d]
+        c = 0.5 * (f[1:] + f[:-1])
+        lo = c[0] - (np.arange(NG, 0, -1)) * (f[1] - f[0])
+        hi = c[-1] + np.arange(1, NG + 1) * (f[-1] - f[-2])
+        return np.concatenate([lo, c, hi])
 
     def mesh(self):
         """Broadcastable (z, y, x) coordinate arrays of shape (pz, py, px)."""
@@ -155,16 +170,19 @@ def _real_sph_harm_sum(theta, phi, coeffs, lmax):
 
 def bubble_collapse_3d(n: int = 128, seed_offset: int = 2, noise: float = 0.01, lmax: int = 8,
                        radius: float = 0.1, centre=(0.5, 0.5, 0.5), p_bubble: float = 1.0e4,
-                       p_water: float = 1.0e6, smear_cells: float = 1.0):
+                       p_water: float = 1.0e6, smear_cells: float = 1.0, stretch: float = 0.0):
     """3D air bubble (radius 0.1 at the box centre, p = 1e4) in water at p = 1e6,
     u = 0, on the unit cube.  The bubble surface R(theta, phi) =
     R0 (1 + noise * S / max|S|) carries seeded real spherical-harmonic noise
     (l = 2..8, a_lm ~ N(0, 1)), and the interface is smeared by
     H = (1 + tanh((r - R)/dx))/2; alpha1 = a_min + (1 - 2 a_min) H, and the
     same H blends the pressure.  noise = 0 gives an exactly centred sphere.
-    n may be an int (cube) or an (nx, ny, nz) tuple on the same unit cube."""
+    n may be an int (cube) or an (nx, ny, nz) tuple on the same unit cube.
+    stretch > 0 refines every dimension around the centre with
+    tanh_faces(n_d, depth=stretch) (the smear then uses the finest width)."""
     ns = (n, n, n) if isinstance(n, int) else tuple(n)
-    spec = GridSpec(ndim=3, n=ns)
+    faces = tuple(tanh_faces(ns[d], depth=stretch) for d in range(3)) if stretch > 0.0 else None
+    spec = GridSpec(ndim=3, n=ns, faces=faces)
     x, y, z = spec.mesh()
     rx, ry, rz = x - centre[0], y - centre[1], z - centre[2]
     r = np.sqrt(rx * rx + ry * ry + rz * rz)
@@ -185,7 +203,8 @@ def bubble_collapse_3d(n: int = 128, seed_offset: int = 2, noise: float = 0.01, 
         R[near] = radius * (1.0 + noise * _real_sph_harm_sum(theta, phi, coeffs, lmax) / smax)
     else:
         R = radius
-    H = _smooth_step(r - R, smear_cells * spec.dx[0])
+    h = spec.dx[0] if faces is None else min(np.diff(f).min() for f in faces)
+    H = _smooth_step(r - R, smear_cells * h)
     alpha1 = ALPHA_MIN + (1.0 - 2.0 * ALPHA_MIN) * H
     p = p_bubble + (p_water - p_bubble) * H
     w = _assemble(spec, alpha1, 1000.0, 1.2, [0.0, 0.0, 0.0], p)
@@ -278,25 +297,41 @@ def ideal_pair():
     return dict(gamma=(1.4, 1.4), pi_inf=(0.0, 0.0))
 
 
-def sine_advection_1d(n: int, amplitude: float = 0.2, u: float = 1.0, p: float = 1.0):
+def sine_advection_1d(n: int, amplitude: float = 0.2, u: float = 1.0, p: float = 1.0, stretch: float = 0.0):
     """Smooth density wave rho = 1 + 0.2 sin(2 pi x) (as exact cell averages)
     advected at u = 1 with uniform p = 1, periodic on [0, 1]; alpha1 = 0.5 and
     both fluids the same ideal gas, so the exact solution is the translate of
-    the initial state.  Each partial density is half the mixture density."""
-    spec = GridSpec(ndim=1, n=(n,), bc=(1, 1, 0, 0, 0, 0), **ideal_pair())
-    x, _, _ = spec.mesh()
-    dx, k = spec.dx[0], 2.0 * math.pi
+    the initial state.  Each partial density is half the mixture density.
+    stretch > 0 puts it on tanh_faces(n, depth=stretch)."""
+    faces = (tanh_faces(n, depth=stretch), None, None) if stretch > 0.0 else None
+    spec = GridSpec(ndim=1, n=(n,), bc=(1, 1, 0, 0, 0, 0), faces=faces, **ideal_pair())
+    xl, xr = _cell_edges(spec)
+    k = 2.0 * math.pi
     # exact cell averages (u and p uniform, so the conserved averages follow)
-    rho = 1.0 + amplitude * (np.cos(k * (x - dx / 2)) - np.cos(k * (x + dx / 2))) / (k * dx)
-    return spec, _assemble(spec, 0.5, rho, rho, [u], p)
+    rho = 1.0 + amplitude * (np.cos(k * xl) - np.cos(k * xr)) / (k * (xr - xl))
+    return spec, _assemble(spec, 0.5, rho[None, None, :], rho[None, None, :], [u], p)
+
+
+def _cell_edges(spec: GridSpec):
+    """Left and right x edges of every padded cell along x (ghost cells of a
+    periodic dimension are the interior cells one period away)."""
+    n = spec.n[0]
+    f = spec.face_coords(0)
+    if f is None:
+        f = spec.lo[0] + np.arange(n + 1) * spec.dx[0]
+    L = spec.hi[0] - spec.lo[0]
+    i = np.arange(-NG, n + NG)
+    j = np.mod(i, n)
+    shift = (i - j) // n * L
+    return f[j] + shift, f[j + 1] + shift
 
 
 def sine_cell_averages(spec: GridSpec, t: float, amplitude: float = 0.2, u: float = 1.0):
     """Exact interior cell averages of the translated sine density at time t."""
-    dx = spec.dx[0]
-    xl = spec.lo[0] + np.arange(spec.n[0]) * dx - u * t
+    xl, xr = _cell_edges(spec)
+    xl, xr = xl[NG:-NG] - u * t, xr[NG:-NG] - u * t
     k = 2.0 * math.pi
-    return 1.0 + amplitude * (np.cos(k * xl) - np.cos(k * (xl + dx))) / (k * dx)
+    return 1.0 + amplitude * (np.cos(k * xl) - np.cos(k * xr)) / (k * (xr - xl))
 
 
 def interface_advection(ndim: int, n: int, u: float = 100.0, p: float = 1.0e5, width_cells: float = 1.0,
@@ -346,6 +381,17 @@ def sod_1d(n: int = 100):
     rho = np.where(left, 1.0, 0.125)
     p = np.where(left, 1.0, 0.1)
     return spec, _assemble(spec, 0.5, rho, rho, [np.zeros_like(x)], p)
+
+
+def tanh_faces(n: int, centre: float = 0.5, width: float = 0.1, depth: float = 0.6, lo: float = 0.0,
+               hi: float = 1.0) -> np.ndarray:
+    """n + 1 face coordinates on [lo, hi] refined around `centre` by a
+    hyperbolic-tangent map: x(s) proportional to s - depth*width*tanh((s - centre)/width)
+    for uniform s, so cells near the centre are (1 - depth) times the far
+    ones (Sec. 4.1 uses tanh stretching to refine locally)."""
+    s = lo + (hi - lo) * np.arange(n + 1) / n
+    g = s - depth * width * np.tanh((s - centre) / width)
+    return lo + (hi - lo) * (g - g[0]) / (g[-1] - g[0])
 
 
 def random_smooth_periodic(ndim: int, n: int, seed_offset: int = 7, modes: int = 3):

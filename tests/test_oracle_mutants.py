@@ -10,7 +10,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mfc_oracle.c")
 PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_units.py", "test_oracle_scheme.py",
-                                                  "test_oracle_kapila.py", "test_oracle_order.py")]
+                                                  "test_oracle_kapila.py", "test_oracle_order.py",
+                                                  "test_oracle_stretched.py")]
 
 MUTANTS = {
     "weno ideal weights swapped": ("dplus[3] = {0.1, 0.6, 0.3}", "dplus[3] = {0.3, 0.6, 0.1}"),
@@ -40,6 +41,11 @@ MUTANTS = {
     "weno3 weight power 1": ("double den = (eps + beta[r]) * (eps + beta[r]);\n        ap[r] = dplus[r] / den;\n        am[r] = dminus[r] / den;\n        sp += ap[r];\n        sm += am[r];\n    }\n    *at_plus",
                              "double den = (eps + beta[r]);\n        ap[r] = dplus[r] / den;\n        am[r] = dminus[r] / den;\n        sp += ap[r];\n        sm += am[r];\n    }\n    *at_plus"),
     "first order from the neighbour": ("*pl = *mi = s[2];", "*pl = *mi = s[3];"),
+    "non-uniform beta second-derivative weight": ("return a1 * a1 + (13.0 / 3.0) * a2 * a2;", "return a1 * a1 + (13.0 / 12.0) * a2 * a2;"),
+    "non-uniform ideal weight cell": ("cf->dplus[2] = qplus[4] / cf->plus[2][2];", "cf->dplus[2] = qplus[3] / cf->plus[2][1];"),
+    "non-uniform cell average of xi^k": ("(pow(hi, k + 1) - pow(lo, k + 1)) / ((k + 1) * (hi - lo))", "(pow(hi, k + 1) - pow(lo, k + 1)) / (k + 1)"),
+    "non-uniform flux difference width": ("double inv_dx = 1.0 / ora_cell_width(g, d, cell);", "double inv_dx = 1.0 / ora_cell_width(g, d, 0);"),
+    "non-uniform cfl width": ("double r = ora_cell_width(g, d, idx[d]) / (fabs(wc[2 + d]) + c);", "double r = ora_cell_width(g, d, 0) / (fabs(wc[2 + d]) + c);"),
     "rhs flux difference sign": ("(Ff[cell * nv + v] - Ff[(cell + 1) * nv + v]) * inv_dx", "(Ff[(cell + 1) * nv + v] - Ff[cell * nv + v]) * inv_dx"),
     "eos Pi without gamma": ("double h1 = g->gamma[0] * g->pi_inf[0]", "double h1 = g->pi_inf[0]"),
     "eos kinetic factor": ("ke += 0.5 * q[2 + m] * w[2 + m];", "ke += q[2 + m] * w[2 + m];"),
