@@ -65,11 +65,11 @@ PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
 
 
-def measured_traffic(kernel, precision, recon, model, n, slot):
+def measured_traffic(kernel, precision, recon, model, stretch, n, slot):
     """(read, write) HBM bytes per launch from the counter runs (WENO5
     kernels only), or None."""
     import hashlib
-    if recon != "weno5" or model != "allaire":
+    if recon != "weno5" or model != "allaire" or stretch:
         return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -86,7 +86,8 @@ def error_vs_reference(spec, w, make_solver, steps, mfc, weights, tau):
     steps of one fixed dt (CFL 0.3 of the initial state) from the same
     initial state; with a network, also the share of interior (cell,
     direction) reconstructions it routes to the linear stencil at the end."""
-    ref = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_SPLIT, precision=mfc.MFC_FP64)
+    ref = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_SPLIT if spec.faces is None else mfc.MFC_KERNEL_FUSED,
+                     precision=mfc.MFC_FP64)
     qr = ref.state_from_prim(w)
     dt = 0.3 * min(spec.dx[:spec.ndim]) / ref.max_wavespeed(qr)
     ref.run(qr, steps, dt=dt)
@@ -211,6 +212,8 @@ def main():
                          "weno3 / first: the third- and first-order reconstructions")
     ap.add_argument("--model", choices=["allaire", "kapila"], default="allaire",
                     help="volume-fraction equation: Allaire (default) or Kapila (with the K div(u) source)")
+    ap.add_argument("--stretch", type=float, default=0.0,
+                    help="tanh stretching depth of the grid around the bubble (0: uniform; needs --kernel fused)")
     ap.add_argument("--tau", type=float, default=None,
                     help="routing threshold on P(smooth) (default: the one stored beside the weights, else 0.5)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2305_09163_amd", "indicator_weights.npy"))
@@ -232,7 +235,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "ensemble":
         return bench_ensemble(args, torch, mfc, W)
-    spec, w = W.bubble_collapse_3d(n=args.n)
+    if args.stretch > 0.0 and args.kernel != "fused":
+        sys.exit("bench.py: stretched grids run on the fused kernel (--kernel fused)")
+    spec, w = W.bubble_collapse_3d(n=args.n, stretch=args.stretch)
     if args.model == "kapila":
         import dataclasses
         spec = dataclasses.replace(spec, model=1)
@@ -300,7 +305,7 @@ def main():
              "frac": achieved / peak_alu, "traffic": None}
         if bound == "hbm":
             r.update(achieved=hbm / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=hbm / PEAK_HBM)
-        tr = measured_traffic(args.kernel, args.precision, args.recon, args.model, args.n, slot)
+        tr = measured_traffic(args.kernel, args.precision, args.recon, args.model, args.stretch, args.n, slot)
         if tr:
             # measured HBM bytes per launch over the same average launch duration
             r.update(traffic=sum(tr) / avg / 1e9, traffic_unit="GB/s",
@@ -325,7 +330,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": f"bubble_collapse_3d_{args.n}", "cells": spec.cells, "nvar": spec.nvar,
                       "cfl": cfl, "precision": args.precision, "kernel": args.kernel, "recon": args.recon,
-                      "model": args.model,
+                      "model": args.model, "stretch": args.stretch,
                       "parallelism": "single GPU"},
            "roofline": roof, "simulated_time_s": t}
     if learned:

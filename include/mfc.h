@@ -106,6 +106,17 @@ typedef struct {
     double weno_eps;     /* WENO5-JS epsilon, > 0 (1e-6 in the paper's setting)    */
     int kernel;          /* MFC_KERNEL_*                                           */
     int model;           /* MFC_MODEL_ALLAIRE or MFC_MODEL_KAPILA                  */
+    const double *faces[3];  /* non-uniform cells (Sec. 4.1): host array of the
+                            n_d + 1 strictly increasing interior face coordinates
+                            along d, copied at mfc_init_grid (lo/hi of that
+                            dimension are then ignored); NULL for uniform cells.
+                            Supported by MFC_KERNEL_FUSED with MFC_RECON_WENO5
+                            (WENO5 with per-cell coefficients from the widths)
+                            or MFC_RECON_FIRST_ORDER; ghost cells take the widths
+                            of the cells the ghost fill copies into them.
+                            With any non-uniform dimension the CFL step is
+                            cfl / max over cells and d of (|u_d| + c)/dx_d(cell),
+                            and mfc_max_wavespeed returns that maximum (1/s). */
 } mfc_grid_desc;
 
 /* Create a grid handle from *desc (validated; see mfc_grid_desc) and
@@ -148,8 +159,10 @@ int mfc_fill_ghosts(mfc_grid *g, void *q, void *stream);
 int mfc_rhs(mfc_grid *g, const void *q, void *rhs, void *stream);
 
 /* Largest signal speed max_cells max_d (|u_d| + c) over interior cells
- * (ghosts not read).  Synchronises the stream and writes *smax_host.
- * Returns MFC_E_NONPHYSICAL if an interior cell is non-physical. */
+ * (ghosts not read); on a grid with non-uniform cells the largest
+ * (|u_d| + c)/dx_d(cell) instead (1/s).  Synchronises the stream and writes
+ * *smax_host.  Returns MFC_E_NONPHYSICAL if an interior cell is
+ * non-physical. */
 int mfc_max_wavespeed(mfc_grid *g, const void *q, double *smax_host, void *stream);
 
 /* One third-order TVD (SSP) Runge-Kutta step in place on q, ghost fill

@@ -513,6 +513,7 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
         if (d.num_fluids != 2) return fail(MFC_E_UNSUPPORTED, "num_fluids must be 2");
         if (d.recon != MFC_RECON_WENO5) return fail(MFC_E_UNSUPPORTED, "batched runs use WENO5");
         if (d.model != MFC_MODEL_ALLAIRE && d.model != MFC_MODEL_KAPILA) return fail(MFC_E_ARG, "unknown model");
+        if (d.faces[0] || d.faces[1]) return fail(MFC_E_UNSUPPORTED, "batched runs use uniform cells");
         for (int k = 0; k < 2; k++) {
             if (d.n[k] < 3 || d.n[k] > (1 << 15)) return fail(MFC_E_ARG, "n must be in [3, 32768]");
             if (!(d.hi[k] > d.lo[k])) return fail(MFC_E_ARG, "hi must exceed lo");
@@ -566,6 +567,8 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
         g.eps = d.weno_eps;
         set_kapila(g, d);
         g.order = 5;
+        g.stretched = 0;
+        for (int k = 0; k < 3; k++) g.wcoef[k] = g.winv[k] = nullptr;
         b->grids.push_back(g);
         dxmin[r] = g.dxmin;
         b->cells += (int64_t)g.n[0] * g.n[1];

@@ -69,13 +69,31 @@ __device__ __forceinline__ bool load_prim(const Grid &g, const T *__restrict__ q
 // Reconstruct one 5-cell stencil for all variables: order ORDER (5 WENO5,
 // 3 WENO3, 1 first order), or the linear fifth-order stencil when lin is set.
 template <int ORDER, int NV, class T>
-__device__ __forceinline__ void recon_regs(const T (&zw)[5][NV], T eps, bool lin, T *plus, T *minus)
+__device__ __forceinline__ void recon_regs(const T (&zw)[5][NV], T eps, bool lin, T *plus, T *minus,
+                                           const double *cf = nullptr)
 {
 #pragma unroll
     for (int v = 0; v < NV; v++) {
         if (lin) linear5_pair<T>(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], plus[v], minus[v]);
-        else recon_pair<ORDER, T>(zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, plus[v], minus[v]);
+        else recon_cell<ORDER, T>(cf, zw[0][v], zw[1][v], zw[2][v], zw[3][v], zw[4][v], eps, plus[v], minus[v]);
     }
+}
+
+// Coefficient row of cell i (-1 <= i <= n_d, clamped for lanes past a ragged
+// edge, whose results are discarded) along d on a non-uniform dimension.
+__device__ __forceinline__ const double *coef_row(const Grid &g, int d, int i)
+{
+    if (!g.wcoef[d]) return nullptr;
+    i = i < -1 ? -1 : (i > g.n[d] ? g.n[d] : i);
+    return g.wcoef[d] + (int64_t)(i + 1) * kStretchCoef;
+}
+
+// Inverse width of interior cell i along d (clamped like coef_row).
+__device__ __forceinline__ double inv_width(const Grid &g, int d, int i)
+{
+    if (!g.winv[d]) return g.inv_dx[d];
+    i = i < 0 ? 0 : (i >= g.n[d] ? g.n[d] - 1 : i);
+    return g.winv[d][i];
 }
 
 // The learned indicator's decision for a stencil held in registers (all lanes
@@ -96,7 +114,7 @@ __device__ __forceinline__ bool route_regs(const mlp::Params &P, uint16_t *scrat
     return mlp::smooth_wave(P, scratch, f, logit_tau, lane);
 }
 
-template <int NDIM, class T, bool ROUTE, int ORDER>
+template <int NDIM, class T, bool ROUTE, int ORDER, bool STRETCH>
 __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
     k_fused(Grid g, const T *__restrict__ q, const T *q0, T *out, int mode, double dt,
             const double *__restrict__ dt_dev, int *__restrict__ flag, int lz, const float *__restrict__ mlpw,
@@ -145,14 +163,14 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
         T plus_prev[NV], mk[NV], dummy[NV];
         bool lin = false;
         if constexpr (ROUTE) lin = route_regs<NDIM, T>(s_mlp, scratch, zw, sqrt_eps, logit_tau, lane);
-        recon_regs<ORDER, NV, T>(zw, eps, lin, plus_prev, dummy);
+        recon_regs<ORDER, NV, T>(zw, eps, lin, plus_prev, dummy, STRETCH ? coef_row(g, 2, z0 - 1) : nullptr);
 #pragma unroll
         for (int p = 0; p < 4; p++)
 #pragma unroll
             for (int v = 0; v < NV; v++) zw[p][v] = zw[p + 1][v];
         bad |= load_prim<NDIM, T>(g, q, cx, cy, z0 + 2, zw[4]);
         if constexpr (ROUTE) lin = route_regs<NDIM, T>(s_mlp, scratch, zw, sqrt_eps, logit_tau, lane);
-        recon_regs<ORDER, NV, T>(zw, eps, lin, pk, mk);
+        recon_regs<ORDER, NV, T>(zw, eps, lin, pk, mk, STRETCH ? coef_row(g, 2, z0) : nullptr);
         bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0), T>(g, plus_prev, mk, Fz, Fz[NV]) && own;
     }
 
@@ -174,7 +192,7 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
             for (int v = 0; v < NV; v++) wk[v] = zw[1][v];
             bool lin = false;
             if constexpr (ROUTE) lin = route_regs<NDIM, T>(s_mlp, scratch, zw, sqrt_eps, logit_tau, lane);
-            recon_regs<ORDER, NV, T>(zw, eps, lin, pn, mn);
+            recon_regs<ORDER, NV, T>(zw, eps, lin, pn, mn, STRETCH ? coef_row(g, 2, k + 1) : nullptr);
             bad |= hllc<NDIM, (NDIM == 3 ? 2 : 0), T>(g, pk, mn, Fzn, Fzn[NV]) && own;
 #pragma unroll
             for (int v = 0; v < NV; v++) pk[v] = pn[v];
@@ -230,10 +248,11 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
             for (int p = tid; p < S::NPX; p += NT) {
                 const int row = p / (TX + 2), c = p % (TX + 2);
                 const int lj = row + OY;
+                const double *cf = STRETCH ? coef_row(g, 0, x0 + c - 1) : nullptr;
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     const T *s = &s_plane[v][lj][c];
-                    recon_pair<ORDER, T>(s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
+                    recon_cell<ORDER, T>(cf, s[0], s[1], s[2], s[3], s[4], eps, s_pair[v][p], s_pair[NV + v][p]);
                 }
             }
         }
@@ -258,9 +277,10 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
         T L[NV], divu;
         {
             const int f = ty * (TX + 1) + tx;
+            const T ix = STRETCH ? T(inv_width(g, 0, gx)) : idx;
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * idx;
-            divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * idx;
+            for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * ix;
+            divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * ix;
         }
 
         if constexpr (NDIM >= 2) {
@@ -295,11 +315,12 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
                 for (int p = tid; p < S::NPY; p += NT) {
                     const int c = p % TX, r = p / TX;
                     const int li = c + NG;
+                    const double *cf = STRETCH ? coef_row(g, 1, y0 + r - 1) : nullptr;
 #pragma unroll
                     for (int v = 0; v < NV; v++)
-                        recon_pair<ORDER, T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
-                                   s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, s_pair[v][p],
-                                   s_pair[NV + v][p]);
+                        recon_cell<ORDER, T>(cf, s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                             s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, s_pair[v][p],
+                                             s_pair[NV + v][p]);
                 }
             }
             __syncthreads();
@@ -320,14 +341,16 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
             }
             __syncthreads();
             const int f = ty * TX + tx;
+            const T iy = STRETCH ? T(inv_width(g, 1, gy)) : idy;
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * idy;
-            divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
+            for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * iy;
+            divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * iy;
         }
         if constexpr (NDIM == 3) {
+            const T iz = STRETCH ? T(inv_width(g, 2, k)) : idz;
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] += (Fz[v] - Fzn[v]) * idz;
-            divu += (Fzn[NV] - Fz[NV]) * idz;
+            for (int v = 0; v < NV; v++) L[v] += (Fz[v] - Fzn[v]) * iz;
+            divu += (Fzn[NV] - Fz[NV]) * iz;
 #pragma unroll
             for (int v = 0; v <= NV; v++) Fz[v] = Fzn[v];
         }
@@ -355,7 +378,7 @@ __global__ void __launch_bounds__(Shape<NDIM>::NT, 2)
     if (bad) atomicOr(flag, 1);
 }
 
-template <int NDIM, class T, bool ROUTE, int ORDER>
+template <int NDIM, class T, bool ROUTE, int ORDER, bool STRETCH>
 int rhs_fused(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s)
 {
     using S = Shape<NDIM>;
@@ -364,22 +387,22 @@ int rhs_fused(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
               NDIM == 3 ? (g.n[2] + kLZ - 1) / kLZ : 1);
     const T se = T(__builtin_sqrt(g.eps));
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_fused<NDIM, T, ROUTE, ORDER>), grid, dim3(S::NT), 0, s, g, q, q0, out, mode, dt, dt_dev, h->flag, kLZ,
+    hipLaunchKernelGGL((k_fused<NDIM, T, ROUTE, ORDER, STRETCH>), grid, dim3(S::NT), 0, s, g, q, q0, out, mode, dt, dt_dev, h->flag, kLZ,
                        h->mlp, h->logit_tau, se);
     timing_end(h, s);
     return hip_status(hipGetLastError(), "fused right-hand side launch");
 }
 
-template <class T, bool ROUTE, int ORDER>
+template <class T, bool ROUTE, int ORDER, bool STRETCH = false>
 int rhs_fused_t(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt, const double *dt_dev,
                 hipStream_t s)
 {
     const T *a = (const T *)q, *b = (const T *)q0;
     T *o = (T *)out;
     switch (h->g.ndim) {
-    case 1: return rhs_fused<1, T, ROUTE, ORDER>(h, a, b, o, mode, dt, dt_dev, s);
-    case 2: return rhs_fused<2, T, ROUTE, ORDER>(h, a, b, o, mode, dt, dt_dev, s);
-    default: return rhs_fused<3, T, ROUTE, ORDER>(h, a, b, o, mode, dt, dt_dev, s);
+    case 1: return rhs_fused<1, T, ROUTE, ORDER, STRETCH>(h, a, b, o, mode, dt, dt_dev, s);
+    case 2: return rhs_fused<2, T, ROUTE, ORDER, STRETCH>(h, a, b, o, mode, dt, dt_dev, s);
+    default: return rhs_fused<3, T, ROUTE, ORDER, STRETCH>(h, a, b, o, mode, dt, dt_dev, s);
     }
 }
 
@@ -391,6 +414,13 @@ int launch_rhs_fused(mfc_grid *h, const void *q, const void *q0, void *out, int 
     const bool learned = h->desc.recon == MFC_RECON_LEARNED;
     if (learned && !h->mlp) return fail(MFC_E_ARG, "MFC_RECON_LEARNED needs mfc_set_indicator first");
     const bool f32 = h->desc.precision == MFC_FP32_MIXED;
+    if (h->g.stretched) {   // WENO5 or first order (validated at init)
+        if (h->desc.recon == MFC_RECON_FIRST_ORDER)
+            return f32 ? rhs_fused_t<float, false, 1, true>(h, q, q0, out, mode, dt, dt_dev, s)
+                       : rhs_fused_t<double, false, 1, true>(h, q, q0, out, mode, dt, dt_dev, s);
+        return f32 ? rhs_fused_t<float, false, 5, true>(h, q, q0, out, mode, dt, dt_dev, s)
+                   : rhs_fused_t<double, false, 5, true>(h, q, q0, out, mode, dt, dt_dev, s);
+    }
     switch (h->desc.recon) {
     case MFC_RECON_LEARNED:
         return f32 ? rhs_fused_t<float, true, 5>(h, q, q0, out, mode, dt, dt_dev, s)

@@ -50,6 +50,10 @@ constexpr int kReduceThreads = 256;
 int fail(int status, const std::string &detail);
 // Kapila coefficients of a grid from its descriptor (model, gamma, pi_inf)
 void set_kapila(Grid &g, const mfc_grid_desc &d);
+// Device tables of a non-uniform grid (stretch.hip): built at init from the
+// descriptor's face coordinates, released with the handle.
+int build_stretch_tables(mfc_grid *h, const mfc_grid_desc *d);
+void free_stretch_tables(mfc_grid *h);
 int hip_status(hipError_t e, const char *what);
 
 // kernel timing: bracket one launch of the dominant kernel

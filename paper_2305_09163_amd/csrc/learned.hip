@@ -313,6 +313,7 @@ int mfc_harvest(mfc_grid *h, void *q, uint16_t *features, uint8_t *labels, doubl
 {
     if (!h || !q || !features || !labels) return fail(MFC_E_ARG, "null argument");
     if (h->desc.precision != MFC_FP64) return fail(MFC_E_UNSUPPORTED, "harvest reads FP64 states");
+    if (h->g.stretched) return fail(MFC_E_UNSUPPORTED, "harvest labels uniform-grid WENO5 weights");
     int st = mfc_fill_ghosts(h, q, stream);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;

@@ -172,8 +172,18 @@ __global__ void __launch_bounds__(kReduceThreads) k_wavespeed(Grid g, const T *_
         double Gam, Pi;
         mixture<double>(g, double(wc[A]), Gam, Pi);
         double cs = __builtin_sqrt(sound2<double>(Gam, Pi, double(wc[0]) + double(wc[1]), double(wc[E])));
+        if (g.stretched) {
+            // non-uniform cells: the largest (|u_d| + c)/dx_d (the CFL step is cfl over it)
+            const int idx[3] = {i, j, k};
 #pragma unroll
-        for (int d = 0; d < NDIM; d++) smax = __builtin_fmax(smax, __builtin_fabs(double(wc[2 + d])) + cs);
+            for (int d = 0; d < NDIM; d++) {
+                const double iw = g.winv[d] ? g.winv[d][idx[d]] : g.inv_dx[d];
+                smax = __builtin_fmax(smax, (__builtin_fabs(double(wc[2 + d])) + cs) * iw);
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < NDIM; d++) smax = __builtin_fmax(smax, __builtin_fabs(double(wc[2 + d])) + cs);
+        }
     }
     if (bad) atomicOr(flag, 2);
 #pragma unroll
@@ -257,6 +267,17 @@ int validate(const mfc_grid_desc *d)
     if (d->kernel == MFC_KERNEL_SPLIT && d->ndim != 3) return fail(MFC_E_UNSUPPORTED, "the split path is 3D only");
     if (d->recon == MFC_RECON_LEARNED && d->kernel == MFC_KERNEL_STAGED)
         return fail(MFC_E_UNSUPPORTED, "the staged path reconstructs with WENO5 only");
+    for (int k = 0; k < d->ndim; k++) {
+        const double *f = d->faces[k];
+        if (!f) continue;
+        if (d->kernel != MFC_KERNEL_FUSED)
+            return fail(MFC_E_UNSUPPORTED, "non-uniform cells need MFC_KERNEL_FUSED");
+        if (d->recon != MFC_RECON_WENO5 && d->recon != MFC_RECON_FIRST_ORDER)
+            return fail(MFC_E_UNSUPPORTED, "non-uniform cells take WENO5 or first order");
+        for (int i = 0; i < d->n[k]; i++)
+            if (!(f[i + 1] > f[i]) || !std::isfinite(f[i]) || !std::isfinite(f[i + 1]))
+                return fail(MFC_E_ARG, "face coordinates must be finite and strictly increasing");
+    }
     return MFC_OK;
 }
 
@@ -372,6 +393,7 @@ int mfc_free_grid(mfc_grid *h)
         if (p) (void)hipFree(p);
     for (auto &ev : h->ev)
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    free_stretch_tables(h);
     delete h;
     return MFC_OK;
 }
@@ -413,6 +435,10 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
     for (int f = 0; f < 6; f++) g.bc[f] = h->desc.bc[f];
     set_kapila(g, *desc);
     g.order = desc->recon == MFC_RECON_WENO3 ? 3 : (desc->recon == MFC_RECON_FIRST_ORDER ? 1 : 5);
+    g.stretched = 0;
+    for (int d = 0; d < desc->ndim; d++) g.stretched |= desc->faces[d] != nullptr;
+    if (g.stretched) g.dxmin = 1.0;   // the reduction then returns max (|u_d| + c)/dx_d
+    for (int d = 0; d < 3; d++) h->desc.faces[d] = nullptr;   // the caller's arrays are not kept
     h->cells_padded = g.vstride;
     h->cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
     if (hipGetDevice(&h->device) != hipSuccess ||
@@ -422,6 +448,11 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
         return fail(MFC_E_HIP, "device query failed");
     }
 
+    if (g.stretched && (st = build_stretch_tables(h, desc)) != MFC_OK) {
+        free_stretch_tables(h);
+        delete h;
+        return st;
+    }
     int64_t sb = state_bytes(h);
     hipError_t e = hipSuccess;
     auto alloc = [&](void **p, int64_t bytes) {

@@ -40,7 +40,14 @@ struct Grid {
     // Kapila alpha1 equation (kapila != 0): rho_k c_k^2 = zg[k] p + zp[k]
     int kapila;
     double zg[2], zp[2];  // gamma_k and gamma_k pi_k
+    // non-uniform cells (device tables; null on a uniform dimension):
+    // wcoef[d][(i + 1) * kStretchCoef ...] the WENO5 coefficients of cell i
+    // (-1 <= i <= n_d), winv[d][i] = 1 / width of interior cell i
+    int stretched;
+    const double *wcoef[3];
+    const double *winv[3];
 };
+constexpr int kStretchCoef = 42;
 
 // ---------------------------------------------------------------- reciprocal
 // Double reciprocal: hardware estimate refined by two Newton-Raphson steps
@@ -265,6 +272,70 @@ __device__ __forceinline__ void recon_pair(T vm2, T vm1, T v0, T vp1, T vp2, T e
         plus = v0;
         minus = v0;
     }
+}
+
+// WENO5 on non-uniform cells from the 42 coefficients of the cell (layout in
+// stretch.hip): candidates, a1 and a2 of each stencil are linear in its
+// three values, beta_r = a1^2 + (13/3) a2^2, ideal weights per face.  FP64
+// directly, FP32 in the ratio form (weights relative to the smallest
+// (eps + beta)).
+template <class T>
+__device__ __forceinline__ void weno5_nonuniform_pair(const double *__restrict__ cf, T vm2, T vm1, T v0, T vp1,
+                                                      T vp2, T eps, T &plus, T &minus)
+{
+    const T s[5] = {vm2, vm1, v0, vp1, vp2};
+    T pp[3], pm[3], e[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        T a1 = T(0), a2 = T(0);
+        pp[r] = pm[r] = T(0);
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            pp[r] = fmaT(T(cf[3 * r + j]), s[r + j], pp[r]);
+            pm[r] = fmaT(T(cf[9 + 3 * r + j]), s[r + j], pm[r]);
+            a1 = fmaT(T(cf[18 + 3 * r + j]), s[r + j], a1);
+            a2 = fmaT(T(cf[27 + 3 * r + j]), s[r + j], a2);
+        }
+        e[r] = eps + fmaT(a1, a1, T(13.0 / 3.0) * a2 * a2);
+    }
+    T wp[3], wm[3], sp = T(0), sm = T(0);
+    if constexpr (std::is_same<T, double>::value) {
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            const T inv = rcp(e[r] * e[r]);
+            wp[r] = T(cf[36 + r]) * inv;
+            wm[r] = T(cf[39 + r]) * inv;
+        }
+    } else {
+        const T emin = __builtin_fminf(e[0], __builtin_fminf(e[1], e[2]));
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            const T t = emin * rcp(e[r]);
+            wp[r] = T(cf[36 + r]) * (t * t);
+            wm[r] = T(cf[39 + r]) * (t * t);
+        }
+    }
+    T np = T(0), nm = T(0);
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        sp += wp[r];
+        sm += wm[r];
+        np = fmaT(wp[r], pp[r], np);
+        nm = fmaT(wm[r], pm[r], nm);
+    }
+    plus = np * rcp(sp);
+    minus = nm * rcp(sm);
+}
+
+// Reconstruction along one direction for a cell whose coefficient row is cf
+// (non-null on a non-uniform dimension, where ORDER 5 takes the non-uniform
+// WENO5 and first order needs no coefficients).
+template <int ORDER, class T>
+__device__ __forceinline__ void recon_cell(const double *cf, T vm2, T vm1, T v0, T vp1, T vp2, T eps, T &plus,
+                                           T &minus)
+{
+    if (ORDER == 5 && cf) weno5_nonuniform_pair<T>(cf, vm2, vm1, v0, vp1, vp2, eps, plus, minus);
+    else recon_pair<ORDER, T>(vm2, vm1, v0, vp1, vp2, eps, plus, minus);
 }
 
 // The linear fifth-order upwind reconstruction (the ideal-weight limit of

@@ -11,6 +11,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MFC_LIB") or os.path.join(HERE, "libmfc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mfc.h")
@@ -39,7 +41,7 @@ class mfc_grid_desc(ctypes.Structure):
                 ("hi", ctypes.c_double * 3), ("num_fluids", ctypes.c_int), ("gamma", ctypes.c_double * 2),
                 ("pi_inf", ctypes.c_double * 2), ("bc", ctypes.c_int * 6), ("precision", ctypes.c_int),
                 ("recon", ctypes.c_int), ("weno_eps", ctypes.c_double), ("kernel", ctypes.c_int),
-                ("model", ctypes.c_int)]
+                ("model", ctypes.c_int), ("faces", ctypes.POINTER(ctypes.c_double) * 3)]
 
 
 class mfc_batch_tune(ctypes.Structure):
@@ -160,6 +162,13 @@ def make_desc(spec, precision: int = MFC_FP64, recon: int = MFC_RECON_WENO5,
     d.weno_eps = spec.weno_eps
     d.kernel = kernel
     d.model = getattr(spec, "model", MFC_MODEL_ALLAIRE)
+    d._keep = []   # face arrays must outlive the init call that copies them
+    for k in range(3):
+        f = spec.face_coords(k) if hasattr(spec, "face_coords") else None
+        if f is not None:
+            f = np.ascontiguousarray(f, dtype=np.float64)
+            d._keep.append(f)
+            d.faces[k] = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return d
 
 

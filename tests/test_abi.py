@@ -150,3 +150,28 @@ def test_learned_recon_rejected_for_staged(L):
     h = ctypes.c_void_p(123)
     d = desc(recon=mfc.MFC_RECON_LEARNED)      # desc() builds a staged-kernel descriptor
     assert L.mfc_init_grid(ctypes.byref(d), ctypes.byref(h)) == mfc.MFC_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("kernel,recon,faces,code", [
+    (mfc.MFC_KERNEL_SPLIT, mfc.MFC_RECON_WENO5, "tanh", mfc.MFC_E_UNSUPPORTED),
+    (mfc.MFC_KERNEL_STAGED, mfc.MFC_RECON_WENO5, "tanh", mfc.MFC_E_UNSUPPORTED),
+    (mfc.MFC_KERNEL_FUSED, mfc.MFC_RECON_WENO3, "tanh", mfc.MFC_E_UNSUPPORTED),
+    (mfc.MFC_KERNEL_FUSED, mfc.MFC_RECON_LEARNED, "tanh", mfc.MFC_E_UNSUPPORTED),
+    (mfc.MFC_KERNEL_FUSED, mfc.MFC_RECON_WENO5, "unsorted", mfc.MFC_E_ARG),
+    (mfc.MFC_KERNEL_FUSED, mfc.MFC_RECON_WENO5, "nan", mfc.MFC_E_ARG),
+])
+def test_init_rejects_unsupported_non_uniform_grids(L, kernel, recon, faces, code):
+    import dataclasses
+    spec, _ = W.bubble_collapse_3d(n=(8, 8, 8))
+    f = W.tanh_faces(8, depth=0.5)
+    if faces == "unsorted":
+        f = f.copy()
+        f[3], f[4] = f[4], f[3]
+    elif faces == "nan":
+        f = f.copy()
+        f[2] = float("nan")
+    spec = dataclasses.replace(spec, faces=(f, None, None))
+    d = mfc.make_desc(spec, kernel=kernel, recon=recon)
+    h = ctypes.c_void_p(123)
+    assert L.mfc_init_grid(ctypes.byref(d), ctypes.byref(h)) == code
+    assert h.value is None
