@@ -55,11 +55,11 @@ SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences)", flops
 # WRITE_SIZE x 1.00).  Valid only for the kernel sources they were taken on;
 # any change to those files turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h")
-TRAFFIC = {"sha256": "c00d3e6ff8a667b396811eb0b18a458220cd7cbd50bb67654e720a55a9eecfbe",
-           ("split", "fp64", 128, 0): (124.72e6, 139.42e6),
-           ("split", "fp64", 128, 1): (508.30e6, 121.61e6),
+TRAFFIC = {"sha256": "bf0bcd97078293f64b21ffb68a15e3f102920b6a30fbb79f9857b70681abe31c",
            ("split", "fp32", 128, 0): (61.78e6, 70.32e6),
-           ("split", "fp32", 128, 1): (248.26e6, 61.55e6)}
+           ("split", "fp32", 128, 1): (245.35e6, 62.54e6),
+           ("split", "fp64", 128, 0): (124.75e6, 139.56e6),
+           ("split", "fp64", 128, 1): (514.17e6, 124.05e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
