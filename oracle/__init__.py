@@ -63,6 +63,7 @@ def lib():
             "ora_mixture": (None, [G, ctypes.c_double, _D, _D]),
             "ora_sound_speed2": (ctypes.c_double, [G, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
             "ora_kapila_K": (ctypes.c_double, [G, _D]),
+            "ora_cbc_cell": (None, [G, ctypes.c_int, ctypes.c_int, _D, _D, _D]),
             "ora_prim_to_cons": (None, [G, _D, _D]),
             "ora_cons_to_prim": (ctypes.c_int, [G, _D, _D]),
             "ora_weno5": (None, [_D, ctypes.c_double, _D, _D, _D]),
@@ -220,6 +221,16 @@ def kapila_K(spec, w_cell):
     w = _arr(w_cell)
     assert w.shape == (spec.nvar,)
     return lib().ora_kapila_K(ctypes.byref(grid(spec)), _ptr(w))
+
+
+def cbc_cell(spec, d: int, side: int, w_cell, dwdx):
+    """Normal-direction conservative time derivative of a characteristic
+    (non-reflecting) boundary cell along d (side 0 low, 1 high) from its
+    primitives and their normal derivative."""
+    w, dw = _arr(w_cell), _arr(dwdx)
+    out = np.empty(spec.nvar)
+    lib().ora_cbc_cell(ctypes.byref(grid(spec)), d, side, _ptr(w), _ptr(dw), _ptr(out))
+    return out
 
 
 def cons_to_prim_field(spec, q):

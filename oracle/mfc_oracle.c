@@ -56,7 +56,10 @@ typedef struct {
     double dx[3];       /* uniform cell width per active dimension        */
     double gamma[2];    /* stiffened-gas gamma of fluids 1 and 2          */
     double pi_inf[2];   /* stiffened-gas pi_infinity of fluids 1 and 2    */
-    int bc[6];          /* x-,x+,y-,y+,z-,z+: 0 extrapolation, 1 periodic */
+    int bc[6];          /* x-,x+,y-,y+,z-,z+: 0 extrapolation, 1 periodic,
+                           2 characteristic non-reflecting (ghosts filled
+                           as for extrapolation; the boundary cell's normal
+                           terms take the characteristic form)            */
     double weno_eps;    /* WENO5-JS epsilon                               */
     int recon;          /* 0 WENO5 everywhere; 1 the linear fifth-order
                            stencil everywhere; 2 per (cell, direction) as
@@ -577,6 +580,67 @@ int ora_fill_ghosts(const ora_grid *g, double *q)
 }
 
 /* ---------------------------------------------------------------------- */
+/* Characteristic boundary condition (Sec. 3.3)                             */
+/* ---------------------------------------------------------------------- */
+
+/* Characteristic-based, non-reflecting treatment of a boundary cell along
+ * dimension d (the paper uses characteristic boundary conditions after
+ * Thompson, time-dependent form).  In the primitive variables the terms
+ * normal to the boundary are written with the wave amplitudes of the
+ * one-dimensional system:
+ *   L1 = (u - c)(p_x - rho c u_x),  L5 = (u + c)(p_x + rho c u_x),
+ *   L_k = u ((alpha_k rho_k)_x - alpha_k rho_k p_x/(rho c^2))   (k = 1, 2),
+ *   L_t = u (u_t)_x for each tangential velocity,  L_a = u (alpha1)_x,
+ * with c the mixture sound speed and u the normal velocity; an amplitude
+ * whose wave travels into the domain is set to zero (no incoming wave),
+ * the others use the one-sided derivative dwdx of the caller.  Then
+ *   p_t = -(L5 + L1)/2,  u_t = -(L5 - L1)/(2 rho c),
+ *   (alpha_k rho_k)_t = -L_k - alpha_k rho_k (L5 + L1)/(2 rho c^2),
+ *   (u_t)_t = -L_t,  (alpha1)_t = -L_a,
+ * converted to the conservative rows through rho E = Gamma(alpha1) p +
+ * Pi(alpha1) + rho |u|^2/2.  side 0: boundary at the low end (the domain
+ * lies at larger coordinates), side 1: at the high end.  dqdt receives the
+ * normal-direction time derivative of the conservative rows. */
+void ora_cbc_cell(const ora_grid *g, int d, int side, const double *w, const double *dwdx, double *dqdt)
+{
+    int nd = g->ndim, nv = 4 + nd;
+    double rho = w[0] + w[1], p = w[nv - 2], alpha1 = w[nv - 1], un = w[2 + d];
+    double c2 = ora_sound_speed2(g, rho, p, alpha1), c = sqrt(c2);
+    double lam1 = un - c, lam5 = un + c, lamm = un;
+    #define ENTERS(l) (side == 0 ? (l) > 0.0 : (l) < 0.0)
+    double dp = dwdx[nv - 2], du = dwdx[2 + d];
+    double L1 = ENTERS(lam1) ? 0.0 : lam1 * (dp - rho * c * du);
+    double L5 = ENTERS(lam5) ? 0.0 : lam5 * (dp + rho * c * du);
+    double Lk[2], Lt[3], La;
+    for (int k = 0; k < 2; k++) Lk[k] = ENTERS(lamm) ? 0.0 : lamm * (dwdx[k] - w[k] / (rho * c2) * dp);
+    for (int m = 0; m < nd; m++) Lt[m] = ENTERS(lamm) ? 0.0 : lamm * dwdx[2 + m];
+    La = ENTERS(lamm) ? 0.0 : lamm * dwdx[nv - 1];
+    #undef ENTERS
+    /* primitive time derivatives */
+    double pt = -0.5 * (L5 + L1);
+    double ut[3];
+    for (int m = 0; m < nd; m++) ut[m] = m == d ? -(L5 - L1) / (2.0 * rho * c) : -Lt[m];
+    double rkt[2];
+    for (int k = 0; k < 2; k++) rkt[k] = -Lk[k] - w[k] / (rho * c2) * 0.5 * (L5 + L1);
+    double at = -La;
+    /* conservative rows */
+    double Gamma, Pi;
+    ora_mixture(g, alpha1, &Gamma, &Pi);
+    double g1 = 1.0 / (g->gamma[0] - 1.0), g2 = 1.0 / (g->gamma[1] - 1.0);
+    double h1 = g->gamma[0] * g->pi_inf[0] / (g->gamma[0] - 1.0), h2 = g->gamma[1] * g->pi_inf[1] / (g->gamma[1] - 1.0);
+    double rhot = rkt[0] + rkt[1], u2 = 0.0, uut = 0.0;
+    dqdt[0] = rkt[0];
+    dqdt[1] = rkt[1];
+    for (int m = 0; m < nd; m++) {
+        dqdt[2 + m] = w[2 + m] * rhot + rho * ut[m];
+        u2 += w[2 + m] * w[2 + m];
+        uut += w[2 + m] * ut[m];
+    }
+    dqdt[2 + nd] = Gamma * pt + ((g1 - g2) * p + (h1 - h2)) * at + 0.5 * u2 * rhot + rho * uut;
+    dqdt[nv - 1] = at;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Right-hand side (Sec. 3.1, eq. fvmdis)                                   */
 /* ---------------------------------------------------------------------- */
 
@@ -694,6 +758,26 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                 /* flux differences and the divergence of the face velocity */
                 for (int cell = 0; cell < n; cell++) {
                     double inv_dx = 1.0 / ora_cell_width(g, d, cell);
+                    int side = cell == 0 && g->bc[2 * d] == 2 ? 0 : (cell == n - 1 && g->bc[2 * d + 1] == 2 ? 1 : -1);
+                    if (side >= 0) {
+                        /* characteristic boundary cell: second-order one-sided
+                         * derivative of the primitives into the domain */
+                        double wc[MAXV], dw[MAXV], dq[MAXV];
+                        int sg = side == 0 ? 1 : -1;
+                        for (int v = 0; v < nv; v++) {
+                            double f[3];
+                            for (int t = 0; t < 3; t++) {
+                                c[d] = cell + sg * t;
+                                f[t] = w[at(g, v, c[0], c[1], c[2])];
+                            }
+                            wc[v] = f[0];
+                            dw[v] = sg * (-3.0 * f[0] + 4.0 * f[1] - f[2]) * 0.5 * inv_dx;
+                        }
+                        c[d] = cell;
+                        ora_cbc_cell(g, d, side, wc, dw, dq);
+                        for (int v = 0; v < nv; v++) rhs[at(g, v, c[0], c[1], c[2])] += dq[v];
+                        continue;   /* no flux difference, no d-part of div(u) */
+                    }
                     c[d] = cell;
                     for (int v = 0; v < nv; v++)
                         rhs[at(g, v, c[0], c[1], c[2])] += (Ff[cell * nv + v] - Ff[(cell + 1) * nv + v]) * inv_dx;

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mfc_oracle.c")
 PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_units.py", "test_oracle_scheme.py",
                                                   "test_oracle_kapila.py", "test_oracle_order.py",
-                                                  "test_oracle_stretched.py")]
+                                                  "test_oracle_stretched.py", "test_oracle_cbc.py")]
 
 MUTANTS = {
     "weno ideal weights swapped": ("dplus[3] = {0.1, 0.6, 0.3}", "dplus[3] = {0.3, 0.6, 0.1}"),
@@ -45,6 +45,13 @@ MUTANTS = {
     "non-uniform ideal weight cell": ("cf->dplus[2] = qplus[4] / cf->plus[2][2];", "cf->dplus[2] = qplus[3] / cf->plus[2][1];"),
     "non-uniform cell average of xi^k": ("(pow(hi, k + 1) - pow(lo, k + 1)) / ((k + 1) * (hi - lo))", "(pow(hi, k + 1) - pow(lo, k + 1)) / (k + 1)"),
     "non-uniform flux difference width": ("double inv_dx = 1.0 / ora_cell_width(g, d, cell);", "double inv_dx = 1.0 / ora_cell_width(g, d, 0);"),
+    "cbc incoming wave kept": ("#define ENTERS(l) (side == 0 ? (l) > 0.0 : (l) < 0.0)", "#define ENTERS(l) (side == 0 ? (l) > 1e300 : (l) < -1e300)"),
+    "cbc entering test reversed": ("#define ENTERS(l) (side == 0 ? (l) > 0.0 : (l) < 0.0)", "#define ENTERS(l) (side == 0 ? (l) < 0.0 : (l) > 0.0)"),
+    "cbc acoustic impedance sign": ("lam1 * (dp - rho * c * du)", "lam1 * (dp + rho * c * du)"),
+    "cbc velocity rate factor": ("-(L5 - L1) / (2.0 * rho * c)", "-(L5 - L1) / (rho * c)"),
+    "cbc partial density coupling": ("rkt[k] = -Lk[k] - w[k] / (rho * c2) * 0.5 * (L5 + L1);", "rkt[k] = -Lk[k];"),
+    "cbc one-sided stencil": ("sg * (-3.0 * f[0] + 4.0 * f[1] - f[2]) * 0.5 * inv_dx", "sg * (-f[0] + f[1]) * inv_dx"),
+    "cbc energy volume-fraction term": ("((g1 - g2) * p + (h1 - h2)) * at", "((g1 - g2) * p) * at"),
     "non-uniform cfl width": ("double r = ora_cell_width(g, d, idx[d]) / (fabs(wc[2 + d]) + c);", "double r = ora_cell_width(g, d, 0) / (fabs(wc[2 + d]) + c);"),
     "rhs flux difference sign": ("(Ff[cell * nv + v] - Ff[(cell + 1) * nv + v]) * inv_dx", "(Ff[(cell + 1) * nv + v] - Ff[cell * nv + v]) * inv_dx"),
     "eos Pi without gamma": ("double h1 = g->gamma[0] * g->pi_inf[0]", "double h1 = g->pi_inf[0]"),
