@@ -624,10 +624,10 @@ void ora_cbc_cell(const ora_grid *g, int d, int side, const double *w, const dou
     for (int k = 0; k < 2; k++) rkt[k] = -Lk[k] - w[k] / (rho * c2) * 0.5 * (L5 + L1);
     double at = -La;
     /* conservative rows */
-    double Gamma, Pi;
+    double Gamma, Pi, G1, P1, G0, P0;
     ora_mixture(g, alpha1, &Gamma, &Pi);
-    double g1 = 1.0 / (g->gamma[0] - 1.0), g2 = 1.0 / (g->gamma[1] - 1.0);
-    double h1 = g->gamma[0] * g->pi_inf[0] / (g->gamma[0] - 1.0), h2 = g->gamma[1] * g->pi_inf[1] / (g->gamma[1] - 1.0);
+    ora_mixture(g, 1.0, &G1, &P1);   /* Gamma and Pi are affine in alpha1: their */
+    ora_mixture(g, 0.0, &G0, &P0);   /* derivatives are the pure-fluid differences */
     double rhot = rkt[0] + rkt[1], u2 = 0.0, uut = 0.0;
     dqdt[0] = rkt[0];
     dqdt[1] = rkt[1];
@@ -636,7 +636,7 @@ void ora_cbc_cell(const ora_grid *g, int d, int side, const double *w, const dou
         u2 += w[2 + m] * w[2 + m];
         uut += w[2 + m] * ut[m];
     }
-    dqdt[2 + nd] = Gamma * pt + ((g1 - g2) * p + (h1 - h2)) * at + 0.5 * u2 * rhot + rho * uut;
+    dqdt[2 + nd] = Gamma * pt + ((G1 - G0) * p + (P1 - P0)) * at + 0.5 * u2 * rhot + rho * uut;
     dqdt[nv - 1] = at;
 }
 

@@ -51,7 +51,7 @@ MUTANTS = {
     "cbc velocity rate factor": ("-(L5 - L1) / (2.0 * rho * c)", "-(L5 - L1) / (rho * c)"),
     "cbc partial density coupling": ("rkt[k] = -Lk[k] - w[k] / (rho * c2) * 0.5 * (L5 + L1);", "rkt[k] = -Lk[k];"),
     "cbc one-sided stencil": ("sg * (-3.0 * f[0] + 4.0 * f[1] - f[2]) * 0.5 * inv_dx", "sg * (-f[0] + f[1]) * inv_dx"),
-    "cbc energy volume-fraction term": ("((g1 - g2) * p + (h1 - h2)) * at", "((g1 - g2) * p) * at"),
+    "cbc energy volume-fraction term": ("((G1 - G0) * p + (P1 - P0)) * at", "((G1 - G0) * p) * at"),
     "non-uniform cfl width": ("double r = ora_cell_width(g, d, idx[d]) / (fabs(wc[2 + d]) + c);", "double r = ora_cell_width(g, d, 0) / (fabs(wc[2 + d]) + c);"),
     "rhs flux difference sign": ("(Ff[cell * nv + v] - Ff[(cell + 1) * nv + v]) * inv_dx", "(Ff[(cell + 1) * nv + v] - Ff[cell * nv + v]) * inv_dx"),
     "eos Pi without gamma": ("double h1 = g->gamma[0] * g->pi_inf[0]", "double h1 = g->pi_inf[0]"),
