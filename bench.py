@@ -65,11 +65,11 @@ PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
 
 
-def measured_traffic(kernel, precision, recon, model, stretch, n, slot):
+def measured_traffic(kernel, precision, recon, model, stretch, n, slot, bc="extrap"):
     """(read, write) HBM bytes per launch from the counter runs (WENO5
     kernels only), or None."""
     import hashlib
-    if recon != "weno5" or model != "allaire" or stretch:
+    if recon != "weno5" or model != "allaire" or stretch or bc != "extrap":
         return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -214,6 +214,9 @@ def main():
                     help="volume-fraction equation: Allaire (default) or Kapila (with the K div(u) source)")
     ap.add_argument("--stretch", type=float, default=0.0,
                     help="tanh stretching depth of the grid around the bubble (0: uniform; needs --kernel fused)")
+    ap.add_argument("--bc", choices=["extrap", "characteristic"], default="extrap",
+                    help="boundary of all six faces: zero-gradient extrapolation (default) or the "
+                         "characteristic non-reflecting form")
     ap.add_argument("--tau", type=float, default=None,
                     help="routing threshold on P(smooth) (default: the one stored beside the weights, else 0.5)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2305_09163_amd", "indicator_weights.npy"))
@@ -241,6 +244,9 @@ def main():
     if args.model == "kapila":
         import dataclasses
         spec = dataclasses.replace(spec, model=1)
+    if args.bc == "characteristic":
+        import dataclasses
+        spec = dataclasses.replace(spec, bc=(mfc.MFC_BC_CHARACTERISTIC,) * 6)
     kernel = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}[args.kernel]
     precision = mfc.MFC_FP64 if args.precision == "fp64" else mfc.MFC_FP32_MIXED
     learned = args.recon == "learned"
@@ -305,7 +311,8 @@ def main():
              "frac": achieved / peak_alu, "traffic": None}
         if bound == "hbm":
             r.update(achieved=hbm / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=hbm / PEAK_HBM)
-        tr = measured_traffic(args.kernel, args.precision, args.recon, args.model, args.stretch, args.n, slot)
+        tr = measured_traffic(args.kernel, args.precision, args.recon, args.model, args.stretch, args.n, slot,
+                              args.bc)
         if tr:
             # measured HBM bytes per launch over the same average launch duration
             r.update(traffic=sum(tr) / avg / 1e9, traffic_unit="GB/s",
@@ -330,7 +337,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": f"bubble_collapse_3d_{args.n}", "cells": spec.cells, "nvar": spec.nvar,
                       "cfl": cfl, "precision": args.precision, "kernel": args.kernel, "recon": args.recon,
-                      "model": args.model, "stretch": args.stretch,
+                      "model": args.model, "stretch": args.stretch, "bc": args.bc,
                       "parallelism": "single GPU"},
            "roofline": roof, "simulated_time_s": t}
     if learned:

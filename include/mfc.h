@@ -57,7 +57,16 @@ enum {
     MFC_E_UNSUPPORTED = -5   /* valid request this build does not implement          */
 };
 
-enum { MFC_BC_EXTRAP = 0, MFC_BC_PERIODIC = 1 };
+/* Boundary condition per face.  EXTRAP: ghost cells copy the adjacent
+ * interior cell; PERIODIC: the cell one period away (both faces of a
+ * dimension); CHARACTERISTIC: non-reflecting characteristic boundary
+ * (Sec. 3.3, Thompson's time-dependent form): ghost cells as for EXTRAP,
+ * and on each boundary cell the finite-volume terms normal to the face are
+ * replaced by the characteristic form of the one-dimensional system, with
+ * wave amplitudes from second-order one-sided differences of the primitives
+ * and every amplitude whose wave enters the domain set to zero (Allaire
+ * model, uniform cells; not in batches). */
+enum { MFC_BC_EXTRAP = 0, MFC_BC_PERIODIC = 1, MFC_BC_CHARACTERISTIC = 2 };
 enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
 /* Reconstruction of the primitive variables at the faces (Sec. 3.2):
  * WENO5-JS (the default), the learned routing between WENO5 and its linear

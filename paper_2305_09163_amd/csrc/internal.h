@@ -53,6 +53,11 @@ void set_kapila(Grid &g, const mfc_grid_desc &d);
 // Device tables of a non-uniform grid (stretch.hip): built at init from the
 // descriptor's face coordinates, released with the handle.
 int build_stretch_tables(mfc_grid *h, const mfc_grid_desc *d);
+// Characteristic boundaries (cbc.hip): whether a face has one, and the
+// post-pass that replaces the boundary cells' normal terms in `out` (the
+// right-hand side for mode 0, else the stage result of that mode).
+bool has_cbc(const mfc_grid *h);
+int launch_cbc(mfc_grid *h, const void *q, void *out, int mode, double dt, const double *dt_dev, hipStream_t s);
 void free_stretch_tables(mfc_grid *h);
 int hip_status(hipError_t e, const char *what);
 

@@ -245,8 +245,16 @@ int validate(const mfc_grid_desc *d)
         if (d->n[k] > (1 << 20)) return fail(MFC_E_ARG, "n too large");
         if (!(d->hi[k] > d->lo[k]) || !std::isfinite(d->hi[k] - d->lo[k])) return fail(MFC_E_ARG, "hi must exceed lo");
         int a = d->bc[2 * k], b = d->bc[2 * k + 1];
-        if ((a != MFC_BC_EXTRAP && a != MFC_BC_PERIODIC) || (b != MFC_BC_EXTRAP && b != MFC_BC_PERIODIC))
-            return fail(MFC_E_ARG, "unknown boundary condition");
+        auto known = [](int x) { return x == MFC_BC_EXTRAP || x == MFC_BC_PERIODIC || x == MFC_BC_CHARACTERISTIC; };
+        if (!known(a) || !known(b)) return fail(MFC_E_ARG, "unknown boundary condition");
+        if (a == MFC_BC_CHARACTERISTIC || b == MFC_BC_CHARACTERISTIC) {
+            if (d->model != MFC_MODEL_ALLAIRE)
+                return fail(MFC_E_UNSUPPORTED, "characteristic boundaries take the Allaire model");
+            for (int e = 0; e < d->ndim; e++)
+                if (d->faces[e]) return fail(MFC_E_UNSUPPORTED, "characteristic boundaries need uniform cells");
+            if (d->recon == MFC_RECON_LEARNED)
+                return fail(MFC_E_UNSUPPORTED, "characteristic boundaries with the learned routing");
+        }
         if ((a == MFC_BC_PERIODIC) != (b == MFC_BC_PERIODIC))
             return fail(MFC_E_ARG, "periodic must be set on both faces of a dimension");
     }
@@ -302,11 +310,14 @@ int by_ndim(int ndim, F f)
 }
 
 int rhs_dispatch(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
-                 const double *dt_dev, hipStream_t s)
+                 const double *dt_dev, hipStream_t s, double cfl = 0.0)
 {
-    if (h->desc.kernel == MFC_KERNEL_STAGED) return launch_rhs_staged(h, q, q0, out, mode, dt, dt_dev, s);
-    if (h->desc.kernel == MFC_KERNEL_SPLIT) return launch_rhs_split(h, q, q0, out, mode, dt, dt_dev, s);
-    return launch_rhs_fused(h, q, q0, out, mode, dt, dt_dev, s);
+    int st;
+    if (h->desc.kernel == MFC_KERNEL_STAGED) st = launch_rhs_staged(h, q, q0, out, mode, dt, dt_dev, s);
+    else if (h->desc.kernel == MFC_KERNEL_SPLIT) st = launch_rhs_split(h, q, q0, out, mode, dt, dt_dev, s, cfl);
+    else st = launch_rhs_fused(h, q, q0, out, mode, dt, dt_dev, s);
+    if (st == MFC_OK && has_cbc(h)) st = launch_cbc(h, q, out, mode, dt, dt_dev, s);
+    return st;
 }
 
 bool is_fp32(const mfc_grid *h) { return h->desc.precision == MFC_FP32_MIXED; }
@@ -598,7 +609,7 @@ int mfc_rk3_step(mfc_grid *h, void *qv, double cfl, double dt, void *stream)
     if (h->desc.kernel == MFC_KERNEL_SPLIT && cfl > 0.0) {
         // the x+y pass of the first stage reduces the wave speeds of q^n and
         // the step size is set before its z pass, the first to use it
-        if ((st = launch_rhs_split(h, q, q, A, 1, 0.0, dt_dev, s, cfl))) return st;
+        if ((st = rhs_dispatch(h, q, q, A, 1, 0.0, dt_dev, s, cfl))) return st;
     } else {
         if (cfl > 0.0) {
             if ((st = wavespeed(h, q, s))) return st;

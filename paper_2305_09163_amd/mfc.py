@@ -23,7 +23,7 @@ MFC_E_NOMEM = -2
 MFC_E_HIP = -3
 MFC_E_NONPHYSICAL = -4
 MFC_E_UNSUPPORTED = -5
-MFC_BC_EXTRAP, MFC_BC_PERIODIC = 0, 1
+MFC_BC_EXTRAP, MFC_BC_PERIODIC, MFC_BC_CHARACTERISTIC = 0, 1, 2
 MFC_FP64, MFC_FP32_MIXED = 0, 1
 MFC_RECON_WENO5, MFC_RECON_LEARNED, MFC_RECON_WENO3, MFC_RECON_FIRST_ORDER = 0, 1, 2, 3
 MFC_KERNEL_FUSED, MFC_KERNEL_STAGED, MFC_KERNEL_SPLIT = 0, 1, 2

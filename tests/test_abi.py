@@ -175,3 +175,31 @@ def test_init_rejects_unsupported_non_uniform_grids(L, kernel, recon, faces, cod
     h = ctypes.c_void_p(123)
     assert L.mfc_init_grid(ctypes.byref(d), ctypes.byref(h)) == code
     assert h.value is None
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(bc=(2, 2, 0, 0, 0, 0), model=mfc.MFC_MODEL_KAPILA), mfc.MFC_E_UNSUPPORTED),
+    (dict(bc=(0, 0, 0, 0, 2, 0), kernel=mfc.MFC_KERNEL_FUSED, recon=mfc.MFC_RECON_LEARNED), mfc.MFC_E_UNSUPPORTED),
+    (dict(bc=(2, 1, 0, 0, 0, 0)), mfc.MFC_E_ARG),       # periodic on one face only
+    (dict(bc=(3, 0, 0, 0, 0, 0)), mfc.MFC_E_ARG),
+])
+def test_init_rejects_unsupported_characteristic_faces(L, kw, code):
+    h = ctypes.c_void_p(123)
+    assert L.mfc_init_grid(ctypes.byref(desc(**kw)), ctypes.byref(h)) == code
+    assert h.value is None
+
+
+def test_characteristic_faces_need_uniform_cells(L):
+    import dataclasses
+    spec, _ = W.bubble_collapse_3d(n=(8, 8, 8))
+    spec = dataclasses.replace(spec, faces=(None, W.tanh_faces(8, depth=0.5), None), bc=(2, 2, 0, 0, 0, 0))
+    d = mfc.make_desc(spec, kernel=mfc.MFC_KERNEL_FUSED)
+    h = ctypes.c_void_p(123)
+    assert L.mfc_init_grid(ctypes.byref(d), ctypes.byref(h)) == mfc.MFC_E_UNSUPPORTED
+    assert h.value is None
+
+
+def test_batch_rejects_characteristic_faces(L):
+    b = ctypes.c_void_p(123)
+    assert L.mfc_batch_init(batch_descs(bc=(2, 2, 0, 0, 0, 0)), 3, ctypes.byref(b)) == mfc.MFC_E_ARG
+    assert b.value is None

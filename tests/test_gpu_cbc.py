@@ -1,0 +1,217 @@
+"""Characteristic non-reflecting boundaries (Sec. 3.3, Thompson's
+time-dependent form) on the GPU against the oracle's: right-hand side and
+one step on 1D/2D/3D workloads with characteristic faces alone, at corners
+and mixed with periodic and extrapolated faces, on every kernel and
+reconstruction order; 200 steps on the benchmark path; the acoustic pulse
+that must leave a tube without reflection; the FP32 form's error; and the
+split path's reading of boundary neighbours without ghost cells."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from parity_util import acoustic_floor, rel_l1, rel_linf, rhs_err
+from paper_2305_09163_amd import mfc
+from paper_2305_09163_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+KERNELS = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}
+RECON = {"weno5": mfc.MFC_RECON_WENO5, "weno3": mfc.MFC_RECON_WENO3, "first": mfc.MFC_RECON_FIRST_ORDER}
+ORACLE_RECON = {"weno5": oracle.RECON_WENO5, "weno3": oracle.RECON_WENO3, "first": oracle.RECON_FIRST}
+ALL = (2, 2, 2, 2, 2, 2)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def with_bc(sw, bc):
+    spec, w = sw
+    return dataclasses.replace(spec, bc=bc), w
+
+
+CASES = {
+    "smooth_1d": lambda: with_bc(W.random_smooth_periodic(1, 40), ALL),
+    "smooth_1d_lo": lambda: with_bc(W.random_smooth_periodic(1, 40), (2, 0, 0, 0, 0, 0)),
+    "smooth_2d_corners": lambda: with_bc(W.random_smooth_periodic(2, 21), ALL),
+    "smooth_2d_mixed": lambda: with_bc(W.random_smooth_periodic(2, 21), (2, 0, 1, 1, 0, 0)),
+    "smooth_3d_corners": lambda: with_bc(W.random_smooth_periodic(3, 17), ALL),
+    "smooth_3d_mixed": lambda: with_bc(W.random_smooth_periodic(3, 17), (1, 1, 2, 0, 0, 2)),
+    "min_3d_3": lambda: with_bc(W.random_smooth_periodic(3, 3), ALL),
+    "supersonic_2d_+": lambda: with_bc(W.supersonic_periodic(2, 20), ALL),
+    "supersonic_3d_-": lambda: with_bc(W.supersonic_periodic(3, 12, sign=-1.0), ALL),
+    "bubble_3d": lambda: with_bc(W.bubble_collapse_3d(n=(17, 15, 17)), ALL),
+    "droplet_2d": lambda: with_bc(W.droplet_shock_2d((17, 17), W.SEED + 21), ALL),
+}
+
+
+def kernels_for(spec):
+    return [k for k in sorted(KERNELS) if k != "split" or spec.ndim == 3]
+
+
+PAIRS = [(name, k) for name, make in CASES.items() for k in kernels_for(make()[0])]
+
+
+def rhs_and_step(spec, w, kernel, recon="weno5", precision=mfc.MFC_FP64):
+    s = mfc.Solver(spec, kernel=KERNELS[kernel], recon=RECON[recon], precision=precision)
+    q = s.state_from_prim(w)
+    s.fill_ghosts(q)
+    r = s.rhs(q).double().cpu().numpy()
+    s.check()
+    q1 = s.state_from_prim(w)
+    s.step(q1, cfl=0.3)
+    s.check()
+    return r, q1.double().cpu().numpy()
+
+
+def oracle_rhs_and_step(spec, w, recon="weno5"):
+    qo = oracle.fill_ghosts(spec, oracle.prim_to_cons_field(spec, w))
+    ro, st = oracle.rhs(spec, qo, recon=ORACLE_RECON[recon])
+    assert st == oracle.OK
+    qn, _, st = oracle.run(spec, oracle.prim_to_cons_field(spec, w), 1, cfl=0.3, recon=ORACLE_RECON[recon])
+    assert st == oracle.OK
+    return qo, ro, qn
+
+
+@pytest.mark.parametrize("name,kernel", PAIRS)
+def test_cbc_rhs_and_step(name, kernel):
+    spec, w = CASES[name]()
+    say(f"[cbc] {name} {spec.n} bc={spec.bc} kernel={kernel}")
+    r, q1 = rhs_and_step(spec, w, kernel)
+    qo, ro, qn = oracle_rhs_and_step(spec, w)
+    err = rhs_err(r, ro, qo, spec)
+    e1 = rel_linf(q1, qn, spec, floor_mom=acoustic_floor(spec, qo))
+    say(f"    rhs err {err.max():.2e}, one-step rel Linf {e1.max():.2e}")
+    assert err.max() <= 1e-12 and e1.max() <= 1e-12
+
+
+def test_cbc_changes_the_boundary_cells():
+    """The cases above are not extrapolation in disguise: on the smooth 2D
+    state the characteristic faces change the boundary cells' right-hand
+    side by far more than the parity tolerance, and no other cell."""
+    spec, w = CASES["smooth_2d_corners"]()
+    r, _ = rhs_and_step(spec, w, "fused")
+    rx, _ = rhs_and_step(dataclasses.replace(spec, bc=(0,) * 6), w, "fused")
+    qo = oracle.fill_ghosts(spec, oracle.prim_to_cons_field(spec, w))
+    d = rhs_err(r, rx, qo, spec)
+    assert d.max() > 1e-6
+    I = (slice(None),) + spec.interior[1:]
+    inner = np.abs(r[I] - rx[I])[:, :, 3:-3, 3:-3]
+    assert inner.max() == 0.0
+
+
+@pytest.mark.parametrize("recon", ["weno3", "first"])
+@pytest.mark.parametrize("name,kernel", [("smooth_2d_corners", "fused"), ("smooth_2d_corners", "staged"),
+                                         ("smooth_3d_mixed", "split"), ("bubble_3d", "split")])
+def test_cbc_other_orders(name, kernel, recon):
+    spec, w = CASES[name]()
+    say(f"[cbc {recon}] {name} kernel={kernel}")
+    r, q1 = rhs_and_step(spec, w, kernel, recon)
+    qo, ro, qn = oracle_rhs_and_step(spec, w, recon)
+    err = rhs_err(r, ro, qo, spec)
+    e1 = rel_linf(q1, qn, spec, floor_mom=acoustic_floor(spec, qo))
+    say(f"    rhs err {err.max():.2e}, one-step rel Linf {e1.max():.2e}")
+    assert err.max() <= 1e-12 and e1.max() <= 1e-12
+
+
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
+def test_cbc_200_steps_3d(kernel):
+    spec, w = CASES["smooth_3d_corners"]()
+    say(f"[cbc 200 steps] {spec.n} kernel={kernel}")
+    s = mfc.Solver(spec, kernel=KERNELS[kernel])
+    q = s.state_from_prim(w)
+    s.run(q, 200, cfl=0.3)
+    s.check()
+    q0 = oracle.prim_to_cons_field(spec, w)
+    qn, t, st = oracle.run(spec, q0, 200, cfl=0.3)
+    assert st == oracle.OK
+    assert abs(s.time()[0] - t) <= 1e-12 * t
+    e = rel_l1(q.cpu().numpy(), qn, spec, floor_mom=acoustic_floor(spec, q0))
+    say(f"    200-step rel L1 {e.max():.2e}")
+    assert e.max() <= 1e-10
+
+
+def pulse(n=200):
+    """Right-running acoustic simple wave of amplitude 1e-3 p0 in air."""
+    spec = W.GridSpec(ndim=1, n=(n,), bc=(2, 2, 0, 0, 0, 0), **W.ideal_pair())
+    x = spec.centres(0)
+    p0, rho0 = 1.0e5, 1.2
+    c = np.sqrt(1.4 * p0 / rho0)
+    dp = 1e-3 * p0 * np.exp(-(((x - 0.5) / 0.05) ** 2))
+    w = np.zeros(spec.shape)
+    rho = rho0 + dp / c ** 2
+    w[0] = w[1] = 0.5 * rho[None, None, :]
+    w[2] = dp / (rho0 * c)
+    w[3] = p0 + dp
+    w[4] = 0.5
+    return spec, w, p0
+
+
+@pytest.mark.parametrize("kernel", ["fused", "staged"])
+def test_pulse_leaves_without_reflection(kernel):
+    spec, w, p0 = pulse()
+    say(f"[cbc pulse] kernel={kernel}")
+    s = mfc.Solver(spec, kernel=KERNELS[kernel])
+    q = s.state_from_prim(w)
+    s.run(q, 1100, cfl=0.4)
+    s.check()
+    wg = torch.empty_like(q)
+    mfc.mfc_cons_to_prim(s.h, q, wg)
+    resid = np.abs(wg[3].cpu().numpy()[spec.interior[1:]] - p0).max()
+    q0 = oracle.prim_to_cons_field(spec, w)
+    qn, _, st = oracle.run(spec, q0, 1100, cfl=0.4)
+    assert st == oracle.OK
+    e = rel_l1(q.cpu().numpy(), qn, spec, floor_mom=acoustic_floor(spec, q0))
+    say(f"    residual {resid / (1e-3 * p0):.2e} of the amplitude, rel L1 vs oracle {e.max():.2e}")
+    assert resid < 1e-4 * 1e-3 * p0
+    assert e.max() <= 1e-10
+
+
+def test_cbc_fp32_error():
+    """FP32 storage with FP64 pressure recovery, 50 steps of the smooth 2D
+    state with characteristic faces on every side, against the oracle in
+    FP64: the same error budget as the periodic FP32 runs (storage
+    rounding 6e-8 per stage, grown over 150 stages)."""
+    spec, w = CASES["smooth_2d_corners"]()
+    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_FUSED, precision=mfc.MFC_FP32_MIXED)
+    q = s.state_from_prim(w)
+    s.run(q, 50, cfl=0.3)
+    s.check()
+    q0 = oracle.prim_to_cons_field(spec, w)
+    qn, _, st = oracle.run(spec, q0, 50, cfl=0.3)
+    assert st == oracle.OK
+    qg = q.double().cpu().numpy()
+    e1 = rel_l1(qg, qn, spec, floor_mom=acoustic_floor(spec, q0))
+    ei = rel_linf(qg, qn, spec, floor_mom=acoustic_floor(spec, q0))
+    say(f"[cbc fp32] rel L1 {e1.max():.2e}, rel Linf {ei.max():.2e}")
+    assert e1.max() <= 1e-5 and ei.max() <= 1e-4
+
+
+@pytest.mark.parametrize("bc", [ALL, (2, 0, 1, 1, 0, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_split_cbc_reads_no_ghost_cell(bc, prec):
+    """With characteristic faces the split path still reads no ghost cell:
+    every ghost set to NaN gives bitwise the filled state's results."""
+    spec, w = W.bubble_collapse_3d(n=(17, 15, 17))
+    spec = dataclasses.replace(spec, bc=bc)
+    say(f"[split cbc, NaN ghosts] bc={bc} {prec}")
+    P = mfc.MFC_FP64 if prec == "fp64" else mfc.MFC_FP32_MIXED
+    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_SPLIT, precision=P)
+    q = s.state_from_prim(w)
+    s.fill_ghosts(q)
+    ghost = torch.ones(q.shape, dtype=torch.bool, device=q.device)
+    ghost[spec.interior] = False
+    qn = q.clone()
+    qn[ghost] = float("nan")
+    I = (slice(None),) + spec.interior[1:]
+    r1, r2 = s.rhs(q), s.rhs(qn)
+    s.check()
+    assert torch.equal(r1[I], r2[I])
+    s.step(q, cfl=0.3)
+    s.step(qn, cfl=0.3)
+    s.check()
+    assert torch.equal(q[I], qn[I])
+    assert torch.isnan(qn[ghost]).all()
