@@ -22,68 +22,103 @@
 namespace mfc {
 namespace {
 
-constexpr int kCbcThreads = 256;
+// 64-thread blocks spread the few boundary cells over every CU; the pass is
+// latency-bound, so each cell's two normal fluxes go to two lanes.
+#ifndef MFC_CBC_THREADS
+#define MFC_CBC_THREADS 64
+#endif
+#ifndef MFC_CBC_WAVES
+#define MFC_CBC_WAVES 2
+#endif
+constexpr int kCbcThreads = MFC_CBC_THREADS;
 
-template <int NDIM, int D, class T, int ORDER>
-__global__ void __launch_bounds__(kCbcThreads)
-    k_cbc(Grid g, int side, const T *__restrict__ q, T *out, int mode, double dt, const double *__restrict__ dt_dev,
-          int *__restrict__ flag)
+// The characteristic faces of a grid: bit f of `mask` is set when face f
+// (x-, x+, y-, y+, z-, z+) is characteristic; start[f] is the index of the
+// face's first boundary cell in the one launch that covers them all (two
+// lanes per cell), start[6] the number of cells.
+struct CbcFaces {
+    int mask;
+    int64_t start[7];
+};
+
+// Index into the four distinct cells of a boundary stencil: cells b - 3 ..
+// b + 3 along D with the non-periodic boundary rule (indices clamped into
+// the interior) are, for the low face (b = 0), cell 0 four times and then
+// cells 1, 2, 3; for the high face (b = n - 1) the mirror image.  W[k] holds
+// cell b + k s (s = +1 low face, -1 high face), so stencil cell o is W[at(o)].
+template <int SIDE>
+__device__ constexpr int at(int o)
+{
+    return SIDE == 0 ? (o <= 3 ? 0 : o - 3) : (o >= 3 ? 0 : 3 - o);
+}
+
+// Change of the stage derivative of boundary cell c (c[D] = its boundary
+// index) from the characteristic face SIDE of dimension D: the
+// characteristic rate minus the finite-volume terms normal to the face.
+template <int NDIM, int D, int SIDE, class T, int ORDER>
+__device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__restrict__ q, T delta[4 + NDIM],
+                                           int half)
 {
     constexpr int NV = 4 + NDIM, A = 3 + NDIM, E = 2 + NDIM;
-    constexpr int O1 = D == 0 ? 1 : 0, O2 = D == 2 ? 1 : 2;
-    const int n1 = O1 < NDIM ? g.n[O1] : 1, n2 = O2 < NDIM ? g.n[O2] : 1;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n1 * n2) return;
-    int c[3] = {0, 0, 0};
-    c[O1] = t % n1;
-    c[O2] = t / n1;
+    constexpr int sg = SIDE == 0 ? 1 : -1;
     const int n = g.n[D];
-    const int b = side == 0 ? 0 : n - 1, sg = side == 0 ? 1 : -1;
+    const int b = SIDE == 0 ? 0 : n - 1;
     const T idx = T(g.inv_dx[D]);
     bool bad = false;
 
-    // primitives of cells b-3 .. b+3 along D (clamped into the interior:
-    // the non-periodic boundary rule)
-    T w[7][NV];
+    T W[4][NV];
 #pragma unroll
-    for (int o = 0; o < 7; o++) {
-        c[D] = min(max(b - 3 + o, 0), n - 1);
+    for (int k = 0; k < 4; k++) {
+        c[D] = min(max(b + k * sg, 0), n - 1);   // n = 3: the third neighbour is clamped
         const int64_t off = (int64_t)(c[2] + g.off[2]) * g.stride[2] + (int64_t)(c[1] + g.off[1]) * g.stride[1] +
                             (c[0] + g.off[0]);
         T qc[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + off];
-        bad |= cons_to_prim<NDIM, T>(g, qc, w[o]);
+        bad |= cons_to_prim<NDIM, T>(g, qc, W[k]);
     }
+    c[D] = b;
 
-    // finite-volume terms normal to the face: fluxes at b-1/2 and b+1/2
-    T pl[NV], mb[NV], pb[NV], mr[NV], dummy[NV];
+    // finite-volume terms normal to the face.  The two lanes of a pair
+    // compute one flux each on the same instruction stream, lane 0 the flux
+    // at b-1/2 (left state: cell b-1 reconstructed from stencil cells 0..4,
+    // right state: cell b from 1..5), lane 1 the flux at b+1/2 (cells b from
+    // 1..5 and b+1 from 2..6), and exchange them.
+    constexpr int i0 = at<SIDE>(0), i1 = at<SIDE>(1), i2 = at<SIDE>(2), i3 = at<SIDE>(3), i4 = at<SIDE>(4),
+                  i5 = at<SIDE>(5), i6 = at<SIDE>(6);
+    T lft[NV], rgt[NV], dummy;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-        recon_pair<ORDER, T>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], T(g.eps), pl[v], dummy[v]);
-        recon_pair<ORDER, T>(w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], T(g.eps), pb[v], mb[v]);
-        recon_pair<ORDER, T>(w[2][v], w[3][v], w[4][v], w[5][v], w[6][v], T(g.eps), dummy[v], mr[v]);
+        const T s0 = half ? W[i1][v] : W[i0][v], s1 = half ? W[i2][v] : W[i1][v], s2 = half ? W[i3][v] : W[i2][v],
+                s3 = half ? W[i4][v] : W[i3][v], s4 = half ? W[i5][v] : W[i4][v], s5 = half ? W[i6][v] : W[i5][v];
+        recon_pair<ORDER, T>(s0, s1, s2, s3, s4, T(g.eps), lft[v], dummy);
+        recon_pair<ORDER, T>(s1, s2, s3, s4, s5, T(g.eps), dummy, rgt[v]);
     }
-    T Flo[NV], Fhi[NV], ulo, uhi;
-    bad |= hllc<NDIM, D, T>(g, pl, mb, Flo, ulo);
-    bad |= hllc<NDIM, D, T>(g, pb, mr, Fhi, uhi);
+    T F[NV], uf;
+    bad |= hllc<NDIM, D, T>(g, lft, rgt, F, uf);
     T fv[NV];
 #pragma unroll
-    for (int v = 0; v < NV; v++) fv[v] = (Flo[v] - Fhi[v]) * idx;
-    fv[A] += w[3][A] * ((uhi - ulo) * idx);
+    for (int v = 0; v < NV; v++) {
+        const T other = __shfl_xor(F[v], 1);
+        fv[v] = (half ? other - F[v] : F[v] - other) * idx;
+    }
+    const T uother = __shfl_xor(uf, 1);
+    fv[A] += W[0][A] * ((half ? uf - uother : uother - uf) * idx);
 
-    // characteristic form on the boundary cell
-    const T *wb = w[3];
+    // characteristic form on the boundary cell: second-order one-sided
+    // differences into the domain
+    const T *wb = W[0];
     T dw[NV];
 #pragma unroll
-    for (int v = 0; v < NV; v++)
-        dw[v] = T(sg) * (T(-3) * wb[v] + T(4) * w[3 + sg][v] - w[3 + 2 * sg][v]) * (T(0.5) * idx);
+    for (int v = 0; v < NV; v++) dw[v] = T(sg) * (T(-3) * wb[v] + T(4) * W[1][v] - W[2][v]) * (T(0.5) * idx);
     T Gam, Pi;
     mixture<T>(g, wb[A], Gam, Pi);
     const T rho = wb[0] + wb[1], p = wb[E], un = wb[2 + D];
     const T c2 = sound2<T>(Gam, Pi, rho, p), cs = sqrtT(c2);
     bad |= nonphysical<T>(rho, c2);
-    auto enters = [&](T lam) { return side == 0 ? lam > T(0) : lam < T(0); };
+    // a wave enters through the low face when it moves to +x, through the
+    // high face when it moves to -x
+    auto enters = [](T lam) { return SIDE == 0 ? lam > T(0) : lam < T(0); };
     const T lam1 = un - cs, lam5 = un + cs;
     const T L1 = enters(lam1) ? T(0) : lam1 * (dw[E] - rho * cs * dw[2 + D]);
     const T L5 = enters(lam5) ? T(0) : lam5 * (dw[E] + rho * cs * dw[2 + D]);
@@ -95,60 +130,114 @@ __global__ void __launch_bounds__(kCbcThreads)
     T ut[NDIM];
 #pragma unroll
     for (int m = 0; m < NDIM; m++) ut[m] = m == D ? -(L5 - L1) * rcp(T(2) * rho * cs) : (in_m ? T(0) : -un * dw[2 + m]);
-    const T pt = -S, at = in_m ? T(0) : -un * dw[A];
+    const T pt = -S, at_ = in_m ? T(0) : -un * dw[A];
     const T rhot = rkt[0] + rkt[1];
-    T dq[NV], u2 = T(0), uut = T(0);
-    dq[0] = rkt[0];
-    dq[1] = rkt[1];
+    T u2 = T(0), uut = T(0);
+    delta[0] += rkt[0] - fv[0];
+    delta[1] += rkt[1] - fv[1];
 #pragma unroll
     for (int m = 0; m < NDIM; m++) {
-        dq[2 + m] = wb[2 + m] * rhot + rho * ut[m];
+        delta[2 + m] += (wb[2 + m] * rhot + rho * ut[m]) - fv[2 + m];
         u2 += wb[2 + m] * wb[2 + m];
         uut += wb[2 + m] * ut[m];
     }
-    dq[E] = Gam * pt + (T(g.g1 - g.g2) * p + T(g.h1 - g.h2)) * at + T(0.5) * u2 * rhot + rho * uut;
-    dq[A] = at;
+    delta[E] += (Gam * pt + (T(g.g1 - g.g2) * p + T(g.h1 - g.h2)) * at_ + T(0.5) * u2 * rhot + rho * uut) - fv[E];
+    delta[A] += at_ - fv[A];
+    return bad;
+}
 
-    // replace the normal finite-volume terms of the stage result
-    c[D] = b;
+// Two lanes per (characteristic face, boundary cell of it).  A cell on
+// several characteristic faces (an edge or corner) belongs to the first of
+// them, whose lane pair adds the changes of all of them in face order: every
+// cell is written by one lane, once, in a fixed order.
+template <int NDIM, class T, int ORDER>
+__global__ void __launch_bounds__(kCbcThreads, MFC_CBC_WAVES)
+    k_cbc(Grid g, CbcFaces F, const T *__restrict__ q, T *out, int mode, double dt, const double *__restrict__ dt_dev,
+          int *__restrict__ flag)
+{
+    constexpr int NV = 4 + NDIM;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = gt >> 1;   // the cell; both lanes of a pair leave or stay together
+    const int half = (int)(gt & 1);
+    if (t >= F.start[6]) return;
+    int my = -1;
+    int64_t first = 0;
+#pragma unroll
+    for (int f = 0; f < 2 * NDIM; f++)
+        if (((F.mask >> f) & 1) && t >= F.start[f]) {
+            my = f;
+            first = F.start[f];
+        }
+    if (my < 0) return;
+    const int D = my >> 1;
+    const int nD = D == 0 ? g.n[0] : (D == 1 ? g.n[1] : g.n[2]);
+    const int b = (my & 1) ? nD - 1 : 0;
+    const int n1 = D == 0 ? g.n[1] : g.n[0];
+    const int64_t local = t - first;
+    const int a = (int)(local % n1), a2 = (int)(local / n1);
+    int c[3];
+    c[0] = D == 0 ? b : a;
+    c[1] = D == 0 ? a : (D == 1 ? b : a2);
+    c[2] = D == 2 ? b : a2;
+    int on = 0;   // bit f: the cell lies on characteristic face f
+#pragma unroll
+    for (int f = 0; f < 2 * NDIM; f++)
+        if (((F.mask >> f) & 1) && c[f >> 1] == ((f & 1) ? g.n[f >> 1] - 1 : 0)) on |= 1 << f;
+    if (on & ((1 << my) - 1)) return;   // an earlier face owns this cell
+
+    T delta[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) delta[v] = T(0);
+    bool bad = false;
+    if (on & 1) bad |= face_delta<NDIM, 0, 0, T, ORDER>(g, c, q, delta, half);
+    if (on & 2) bad |= face_delta<NDIM, 0, 1, T, ORDER>(g, c, q, delta, half);
+    if constexpr (NDIM >= 2) {
+        if (on & 4) bad |= face_delta<NDIM, 1, 0, T, ORDER>(g, c, q, delta, half);
+        if (on & 8) bad |= face_delta<NDIM, 1, 1, T, ORDER>(g, c, q, delta, half);
+    }
+    if constexpr (NDIM == 3) {
+        if (on & 16) bad |= face_delta<NDIM, 2, 0, T, ORDER>(g, c, q, delta, half);
+        if (on & 32) bad |= face_delta<NDIM, 2, 1, T, ORDER>(g, c, q, delta, half);
+    }
+
     const int64_t off = (int64_t)(c[2] + g.off[2]) * g.stride[2] + (int64_t)(c[1] + g.off[1]) * g.stride[1] +
                         (c[0] + g.off[0]);
     const T w_dt = mode == 0 ? T(1) : T((mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0)) * (dt_dev ? *dt_dev : dt));
+    if (half) {
 #pragma unroll
-    for (int v = 0; v < NV; v++) out[v * g.vstride + off] += w_dt * (dq[v] - fv[v]);
+        for (int v = 0; v < NV; v++) out[v * g.vstride + off] += w_dt * delta[v];
+    }
     if (bad) atomicOr(flag, 1);
-}
-
-template <int NDIM, class T, int ORDER>
-void launch_faces(mfc_grid *h, const T *q, T *out, int mode, double dt, const double *dt_dev, hipStream_t s)
-{
-    const Grid &g = h->g;
-    for (int d = 0; d < NDIM; d++)
-        for (int side = 0; side < 2; side++) {
-            if (g.bc[2 * d + side] != MFC_BC_CHARACTERISTIC) continue;
-            const int n1 = d == 0 ? g.n[1] : g.n[0], n2 = d == 2 ? g.n[1] : g.n[2];
-            const dim3 grid((unsigned)((int64_t)n1 * n2 + kCbcThreads - 1) / kCbcThreads);
-            if (d == 0)
-                hipLaunchKernelGGL((k_cbc<NDIM, 0, T, ORDER>), grid, dim3(kCbcThreads), 0, s, g, side, q, out, mode,
-                                   dt, dt_dev, h->flag);
-            else if (d == 1)
-                hipLaunchKernelGGL((k_cbc<NDIM, (NDIM >= 2 ? 1 : 0), T, ORDER>), grid, dim3(kCbcThreads), 0, s, g,
-                                   side, q, out, mode, dt, dt_dev, h->flag);
-            else
-                hipLaunchKernelGGL((k_cbc<NDIM, (NDIM == 3 ? 2 : 0), T, ORDER>), grid, dim3(kCbcThreads), 0, s, g,
-                                   side, q, out, mode, dt, dt_dev, h->flag);
-        }
 }
 
 template <class T, int ORDER>
 void launch_t(mfc_grid *h, const void *q, void *out, int mode, double dt, const double *dt_dev, hipStream_t s)
 {
+    const Grid &g = h->g;
+    CbcFaces F{};
+    int64_t total = 0;
+    for (int f = 0; f < 6; f++) {
+        F.start[f] = total;
+        if (f >= 2 * g.ndim || g.bc[f] != MFC_BC_CHARACTERISTIC) continue;
+        const int d = f >> 1;
+        F.mask |= 1 << f;
+        // inactive dimensions have n = 1
+        total += (int64_t)(d == 0 ? g.n[1] : g.n[0]) * (d == 2 ? g.n[1] : g.n[2]);
+    }
+    F.start[6] = total;
+    if (F.mask == 0) return;
+    const dim3 grid((unsigned)((2 * total + kCbcThreads - 1) / kCbcThreads));
     const T *a = (const T *)q;
     T *o = (T *)out;
-    switch (h->g.ndim) {
-    case 1: launch_faces<1, T, ORDER>(h, a, o, mode, dt, dt_dev, s); break;
-    case 2: launch_faces<2, T, ORDER>(h, a, o, mode, dt, dt_dev, s); break;
-    default: launch_faces<3, T, ORDER>(h, a, o, mode, dt, dt_dev, s);
+    switch (g.ndim) {
+    case 1:
+        hipLaunchKernelGGL((k_cbc<1, T, ORDER>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev, h->flag);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_cbc<2, T, ORDER>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev, h->flag);
+        break;
+    default:
+        hipLaunchKernelGGL((k_cbc<3, T, ORDER>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev, h->flag);
     }
 }
 
