@@ -15,7 +15,8 @@ x+y kernel of the split path, or the single fused kernel) with HIP events
 recorded by the library around every launch of it on the launch stream
 during the timed region; `roofline_second_kernel` does the same for the z +
 stage-update kernel of the split path.  `cpu_baseline` times the FP64 CPU
-oracle on the host for one SSP-RK3 step of the same workload.
+oracle on the host for one SSP-RK3 step of the same workload (single-threaded,
+and with OpenMP on every host core under `all_cores`).
 
     python bench.py [--steps K] [--warmup W] [--n 128] [--kernel split|fused|staged]
 """
@@ -111,17 +112,30 @@ def error_vs_reference(spec, w, make_solver, steps, mfc, weights, tau):
 
 
 def cpu_baseline(spec, w):
+    """The FP64 oracle on the host for one SSP-RK3 step of the same workload:
+    the plain single-threaded build, and the OpenMP build of the same source
+    on every host core it is given (OMP_NUM_THREADS, else all cores)."""
     import oracle
 
-    q = oracle.prim_to_cons_field(spec, w)
-    t0 = time.perf_counter()
-    _, _, st = oracle.run(spec, q, 1, cfl=0.3)
-    el = time.perf_counter() - t0
-    assert st == oracle.OK
+    def one_step():
+        q = oracle.prim_to_cons_field(spec, w)
+        t0 = time.perf_counter()
+        _, _, st = oracle.run(spec, q, 1, cfl=0.3)
+        el = time.perf_counter() - t0
+        assert st == oracle.OK
+        return el
+
+    el = one_step()
+    with oracle.threaded() as threads:
+        el_t = one_step()
+    sample = f"1 SSP-RK3 step (3 RHS evaluations) of the {spec.n[0]}^3 bubble workload"
     return {"value": spec.cells * 3 / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 SSP-RK3 step (3 RHS evaluations) of the {spec.n[0]}^3 bubble workload, "
-                      f"single-threaded C oracle (gcc -O2), {el:.1f} s",
-            "host_cpus": os.cpu_count()}
+            "sample": f"{sample}, single-threaded C oracle (gcc -O2), {el:.1f} s",
+            "host_cpus": os.cpu_count(),
+            "all_cores": {"value": spec.cells * 3 / el_t, "unit": "cell-updates/s", "cores": threads,
+                          "kind": "oracle",
+                          "sample": f"{sample}, the same oracle built with OpenMP over the pencils of each "
+                                    f"sweep, {threads} threads, {el_t:.2f} s"}}
 
 
 def bench_ensemble(args, torch, mfc, W):

@@ -12,6 +12,7 @@ it.  Grid arguments are any object with the attributes ``ndim``, ``n``,
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -21,19 +22,25 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mfc_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_lib_omp = None
+_threaded = False
 
 OK = 0
 E_NONPHYSICAL = -4
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
-                        "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB_PATH)
+    """Compile the oracle with gcc (no fast-math, no FMA contraction), once
+    plain and once with OpenMP (the same source: its pragmas spread the
+    pencils of a sweep over threads; results are bitwise the same)."""
+    for path, extra in ((_LIB_PATH, []), (_LIB_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
+                            *extra, "-o", tmp, _SRC, "-lm"], check=True)
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
@@ -47,46 +54,71 @@ class _Grid(ctypes.Structure):
                 ("smooth", ctypes.POINTER(ctypes.c_ubyte)), ("model", ctypes.c_int), ("faces", _D * 3)]
 
 
+@contextlib.contextmanager
+def threaded():
+    """Run the oracle calls inside the block on the OpenMP build (as many
+    threads as OpenMP gives, OMP_NUM_THREADS or all cores); yields that
+    number."""
+    global _threaded
+    prev = _threaded
+    _threaded = True
+    try:
+        yield lib().ora_threads()
+    finally:
+        _threaded = prev
+
+
 def lib():
-    global _lib
+    global _lib, _lib_omp
+    if _threaded:
+        if _lib_omp is None:
+            if not os.path.exists(_LIB_OMP_PATH) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB_OMP_PATH):
+                build(force=True)
+            _lib_omp = _load(_LIB_OMP_PATH)
+        return _lib_omp
     if _lib is None:
         path = os.environ.get("MFC_ORACLE_LIB")  # a deliberately broken build, for mutation tests
         if not path:
             path = _LIB_PATH
             if not os.path.exists(path) or os.path.getmtime(_SRC) > os.path.getmtime(path):
                 build(force=True)   # missing, or older than its source
-        L = ctypes.CDLL(path)
-        G = ctypes.POINTER(_Grid)
-        sig = {
-            "ora_nvar": (ctypes.c_int, [ctypes.c_int]),
-            "ora_padded_cells": (ctypes.c_int64, [G]),
-            "ora_mixture": (None, [G, ctypes.c_double, _D, _D]),
-            "ora_sound_speed2": (ctypes.c_double, [G, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
-            "ora_kapila_K": (ctypes.c_double, [G, _D]),
-            "ora_cbc_cell": (None, [G, ctypes.c_int, ctypes.c_int, _D, _D, _D]),
-            "ora_prim_to_cons": (None, [G, _D, _D]),
-            "ora_cons_to_prim": (ctypes.c_int, [G, _D, _D]),
-            "ora_weno5": (None, [_D, ctypes.c_double, _D, _D, _D]),
-            "ora_linear5": (None, [_D, _D, _D]),
-            "ora_weno3": (None, [_D, ctypes.c_double, _D, _D]),
-            "ora_weno5_nonuniform_cell": (None, [_D, _D, ctypes.c_double, _D, _D]),
-            "ora_weno5_nonuniform_betas": (None, [_D, _D, _D]),
-            "ora_hllc": (ctypes.c_int, [G, ctypes.c_int, _D, _D, _D, _D]),
-            "ora_fill_ghosts": (ctypes.c_int, [G, _D]),
-            "ora_rhs": (ctypes.c_int, [G, _D, _D]),
-            "ora_rk3_combine": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _D, _D, _D, ctypes.c_double, _D]),
-            "ora_max_wavespeed": (ctypes.c_int, [G, _D, _D]),
-            "ora_rk3_step": (ctypes.c_int, [G, _D, ctypes.c_double]),
-            "ora_run": (ctypes.c_int, [G, _D, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]),
-            "ora_prim_to_cons_field": (ctypes.c_int, [G, _D, _D]),
-            "ora_cons_to_prim_field": (ctypes.c_int, [G, _D, _D]),
-        }
-        for name, (res, args) in sig.items():
-            f = getattr(L, name)
-            f.restype = res
-            f.argtypes = args
-        _lib = L
+        _lib = _load(path)
     return _lib
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    G = ctypes.POINTER(_Grid)
+    sig = {
+        "ora_nvar": (ctypes.c_int, [ctypes.c_int]),
+        "ora_padded_cells": (ctypes.c_int64, [G]),
+        "ora_mixture": (None, [G, ctypes.c_double, _D, _D]),
+        "ora_sound_speed2": (ctypes.c_double, [G, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+        "ora_kapila_K": (ctypes.c_double, [G, _D]),
+        "ora_cbc_cell": (None, [G, ctypes.c_int, ctypes.c_int, _D, _D, _D]),
+        "ora_prim_to_cons": (None, [G, _D, _D]),
+        "ora_cons_to_prim": (ctypes.c_int, [G, _D, _D]),
+        "ora_weno5": (None, [_D, ctypes.c_double, _D, _D, _D]),
+        "ora_linear5": (None, [_D, _D, _D]),
+        "ora_weno3": (None, [_D, ctypes.c_double, _D, _D]),
+        "ora_weno5_nonuniform_cell": (None, [_D, _D, ctypes.c_double, _D, _D]),
+        "ora_weno5_nonuniform_betas": (None, [_D, _D, _D]),
+        "ora_hllc": (ctypes.c_int, [G, ctypes.c_int, _D, _D, _D, _D]),
+        "ora_fill_ghosts": (ctypes.c_int, [G, _D]),
+        "ora_rhs": (ctypes.c_int, [G, _D, _D]),
+        "ora_rk3_combine": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _D, _D, _D, ctypes.c_double, _D]),
+        "ora_max_wavespeed": (ctypes.c_int, [G, _D, _D]),
+        "ora_rk3_step": (ctypes.c_int, [G, _D, ctypes.c_double]),
+        "ora_run": (ctypes.c_int, [G, _D, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]),
+        "ora_prim_to_cons_field": (ctypes.c_int, [G, _D, _D]),
+        "ora_cons_to_prim_field": (ctypes.c_int, [G, _D, _D]),
+        "ora_threads": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
 
 
 RECON_WENO5, RECON_LINEAR, RECON_MASK, RECON_WENO3, RECON_FIRST = 0, 1, 2, 3, 4

@@ -41,6 +41,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_OK 0
 #define ORA_E_ARG (-1)
@@ -653,6 +656,18 @@ void ora_cbc_cell(const ora_grid *g, int d, int side, const double *w, const dou
  * with model 1 (Kapila) the alpha1 row carries (alpha1 + K)_cell div(u),
  * i.e. h = -(alpha1 + K), from u . grad(alpha1) = K div(u).
  * Ghost entries of rhs are not written. */
+/* Threads of the OpenMP build (1 in the plain build, where the pragmas
+ * below are ignored).  Every parallel loop writes disjoint cells, so the
+ * two builds give bitwise the same results. */
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int ora_rhs(const ora_grid *g, const double *q, double *rhs)
 {
     int nd = g->ndim, nv = 4 + nd;
@@ -663,14 +678,8 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
     double *divu = calloc(ncell, sizeof(double));
     int nmax = nx > ny ? nx : ny;
     if (nz > nmax) nmax = nz;
-    /* per-pencil work: reconstructed values at both faces of each cell,
-     * and fluxes at the faces */
-    double *rp = malloc(sizeof(double) * (nmax + 2) * nv);
-    double *rm = malloc(sizeof(double) * (nmax + 2) * nv);
-    double *Ff = malloc(sizeof(double) * (nmax + 1) * nv);
-    double *uf = malloc(sizeof(double) * (nmax + 1));
-    if (!w || !divu || !rp || !rm || !Ff || !uf) {
-        free(w); free(divu); free(rp); free(rm); free(Ff); free(uf);
+    if (!w || !divu) {
+        free(w); free(divu);
         return ORA_E_NOMEM;
     }
 
@@ -681,6 +690,7 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
         lo[d] = d < nd ? -NG : 0;
         hi[d] = d < nd ? g->n[d] + NG : 1;
     }
+    #pragma omp parallel for reduction(min : status) schedule(static)
     for (int k = lo[2]; k < hi[2]; k++)
         for (int j = lo[1]; j < hi[1]; j++)
             for (int i = lo[0]; i < hi[0]; i++) {
@@ -719,8 +729,21 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                 ora_weno_coef_nonuniform(wd, &cf[cell + 1]);
             }
         }
+        int pencil_status = ORA_OK;
+        #pragma omp parallel
+        {
+        /* per-pencil work: reconstructed values at both faces of each
+         * cell, and fluxes at the faces (one set per thread) */
+        int mine = ORA_OK;
+        double *rp = malloc(sizeof(double) * (nmax + 2) * nv);
+        double *rm = malloc(sizeof(double) * (nmax + 2) * nv);
+        double *Ff = malloc(sizeof(double) * (nmax + 1) * nv);
+        double *uf = malloc(sizeof(double) * (nmax + 1));
+        if (!rp || !rm || !Ff || !uf) mine = ORA_E_NOMEM;
+        #pragma omp for schedule(static)
         for (int b = 0; b < n2; b++)
             for (int a = 0; a < n1; a++) {
+                if (mine == ORA_E_NOMEM) continue;
                 int c[3];
                 c[o1] = a;
                 c[o2] = b;
@@ -753,7 +776,7 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                  * from cell f-1 (its + face), right state from cell f */
                 for (int f = 0; f <= n; f++) {
                     if (ora_hllc(g, d, &rp[f * nv], &rm[(f + 1) * nv], &Ff[f * nv], &uf[f]) != ORA_OK)
-                        status = ORA_E_NONPHYSICAL;
+                        mine = ORA_E_NONPHYSICAL;
                 }
                 /* flux differences and the divergence of the face velocity */
                 for (int cell = 0; cell < n; cell++) {
@@ -784,10 +807,17 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                     divu[at(g, 0, c[0], c[1], c[2])] += (uf[cell + 1] - uf[cell]) * inv_dx;
                 }
             }
+        free(rp); free(rm); free(Ff); free(uf);
+        #pragma omp critical
+        if (mine < pencil_status) pencil_status = mine;
+        }
+        if (pencil_status < status) status = pencil_status;
         free(cf);
+        if (status == ORA_E_NOMEM) break;
     }
     /* non-conservative source: -h div(u) with h = -alpha1 (Allaire) or
      * h = -(alpha1 + K) (Kapila) on the alpha1 row */
+    #pragma omp parallel for schedule(static)
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < ny; j++)
             for (int i = 0; i < nx; i++) {
@@ -801,7 +831,7 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                 rhs[at(g, nv - 1, i, j, k)] += h * divu[at(g, 0, i, j, k)];
             }
 
-    free(w); free(divu); free(rp); free(rm); free(Ff); free(uf);
+    free(w); free(divu);
     return status;
 }
 
