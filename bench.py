@@ -56,11 +56,11 @@ SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences)", flops
 # WRITE_SIZE x 1.00).  Valid only for the kernel sources they were taken on;
 # any change to those files turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h")
-TRAFFIC = {"sha256": "bf0bcd97078293f64b21ffb68a15e3f102920b6a30fbb79f9857b70681abe31c",
+TRAFFIC = {"sha256": "8dcfd0e281460e3dec5a3f3bed62005c46fac3faba04d121f45b68d05ab9ecce",
            ("split", "fp32", 128, 0): (61.78e6, 70.32e6),
-           ("split", "fp32", 128, 1): (245.35e6, 62.54e6),
-           ("split", "fp64", 128, 0): (124.75e6, 139.56e6),
-           ("split", "fp64", 128, 1): (514.17e6, 124.05e6)}
+           ("split", "fp32", 128, 1): (245.26e6, 62.52e6),
+           ("split", "fp64", 128, 0): (124.72e6, 139.53e6),
+           ("split", "fp64", 128, 1): (514.63e6, 124.19e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
@@ -353,7 +353,7 @@ def main():
                       "cfl": cfl, "precision": args.precision, "kernel": args.kernel, "recon": args.recon,
                       "model": args.model, "stretch": args.stretch, "bc": args.bc,
                       "parallelism": "single GPU"},
-           "roofline": roof, "simulated_time_s": t}
+           "roofline": roof, "simulated_time_s": t, "cell_steps_per_s": value / 3}
     if learned:
         out["config"]["tau"] = args.tau
     if roof_z:
