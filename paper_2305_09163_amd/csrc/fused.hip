@@ -79,23 +79,6 @@ __device__ __forceinline__ void recon_regs(const T (&zw)[5][NV], T eps, bool lin
     }
 }
 
-// Coefficient row of cell i (-1 <= i <= n_d, clamped for lanes past a ragged
-// edge, whose results are discarded) along d on a non-uniform dimension.
-__device__ __forceinline__ const double *coef_row(const Grid &g, int d, int i)
-{
-    if (!g.wcoef[d]) return nullptr;
-    i = i < -1 ? -1 : (i > g.n[d] ? g.n[d] : i);
-    return g.wcoef[d] + (int64_t)(i + 1) * kStretchCoef;
-}
-
-// Inverse width of interior cell i along d (clamped like coef_row).
-__device__ __forceinline__ double inv_width(const Grid &g, int d, int i)
-{
-    if (!g.winv[d]) return g.inv_dx[d];
-    i = i < 0 ? 0 : (i >= g.n[d] ? g.n[d] - 1 : i);
-    return g.winv[d][i];
-}
-
 // The learned indicator's decision for a stencil held in registers (all lanes
 // of the wavefront must call).
 template <int NDIM, class T>

@@ -278,8 +278,8 @@ int validate(const mfc_grid_desc *d)
     for (int k = 0; k < d->ndim; k++) {
         const double *f = d->faces[k];
         if (!f) continue;
-        if (d->kernel != MFC_KERNEL_FUSED)
-            return fail(MFC_E_UNSUPPORTED, "non-uniform cells need MFC_KERNEL_FUSED");
+        if (d->kernel == MFC_KERNEL_STAGED)
+            return fail(MFC_E_UNSUPPORTED, "non-uniform cells need the fused or the split kernel");
         if (d->recon != MFC_RECON_WENO5 && d->recon != MFC_RECON_FIRST_ORDER)
             return fail(MFC_E_UNSUPPORTED, "non-uniform cells take WENO5 or first order");
         for (int i = 0; i < d->n[k]; i++)

@@ -287,10 +287,11 @@ __device__ __forceinline__ void recon_pair(T vm2, T vm1, T v0, T vp1, T vp2, T e
 // stretch.hip): candidates, a1 and a2 of each stencil are linear in its
 // three values, beta_r = a1^2 + (13/3) a2^2, ideal weights per face.  FP64
 // directly, FP32 in the ratio form (weights relative to the smallest
-// (eps + beta)).
-template <class T>
-__device__ __forceinline__ void weno5_nonuniform_pair(const double *__restrict__ cf, T vm2, T vm1, T v0, T vp1,
-                                                      T vp2, T eps, T &plus, T &minus)
+// (eps + beta)).  CF is the row in memory, or a copy of it in registers
+// (one load per cell for all its variables).
+template <class T, class CF>
+__device__ __forceinline__ void weno5_nonuniform_pair(const CF &cf, T vm2, T vm1, T v0, T vp1, T vp2, T eps, T &plus,
+                                                      T &minus)
 {
     const T s[5] = {vm2, vm1, v0, vp1, vp2};
     T pp[3], pm[3], e[3];
@@ -345,6 +346,48 @@ __device__ __forceinline__ void recon_cell(const double *cf, T vm2, T vm1, T v0,
 {
     if (ORDER == 5 && cf) weno5_nonuniform_pair<T>(cf, vm2, vm1, v0, vp1, vp2, eps, plus, minus);
     else recon_pair<ORDER, T>(vm2, vm1, v0, vp1, vp2, eps, plus, minus);
+}
+
+// The coefficient row of a cell copied into registers, in the arithmetic's
+// type (a uniform dimension has none: the flag is false).
+template <class T>
+struct CoefRegs {
+    T c[kStretchCoef];
+    bool on;
+    __device__ __forceinline__ T operator[](int i) const { return c[i]; }
+};
+template <class T>
+__device__ __forceinline__ void load_coefs(const double *__restrict__ cf, CoefRegs<T> &r)
+{
+    r.on = cf != nullptr;
+    if (r.on) {
+#pragma unroll
+        for (int i = 0; i < kStretchCoef; i++) r.c[i] = T(cf[i]);
+    }
+}
+template <int ORDER, class T>
+__device__ __forceinline__ void recon_cell(const CoefRegs<T> &cf, T vm2, T vm1, T v0, T vp1, T vp2, T eps, T &plus,
+                                           T &minus)
+{
+    if (ORDER == 5 && cf.on) weno5_nonuniform_pair<T>(cf, vm2, vm1, v0, vp1, vp2, eps, plus, minus);
+    else recon_pair<ORDER, T>(vm2, vm1, v0, vp1, vp2, eps, plus, minus);
+}
+
+// Coefficient row of cell i (-1 <= i <= n_d, clamped for lanes past a ragged
+// edge, whose results are discarded) along d on a non-uniform dimension.
+__device__ __forceinline__ const double *coef_row(const Grid &g, int d, int i)
+{
+    if (!g.wcoef[d]) return nullptr;
+    i = i < -1 ? -1 : (i > g.n[d] ? g.n[d] : i);
+    return g.wcoef[d] + (int64_t)(i + 1) * kStretchCoef;
+}
+
+// Inverse width of interior cell i along d (clamped like coef_row).
+__device__ __forceinline__ double inv_width(const Grid &g, int d, int i)
+{
+    if (!g.winv[d]) return g.inv_dx[d];
+    i = i < 0 ? 0 : (i >= g.n[d] ? g.n[d] - 1 : i);
+    return g.winv[d][i];
 }
 
 // The linear fifth-order upwind reconstruction (the ideal-weight limit of

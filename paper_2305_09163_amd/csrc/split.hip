@@ -152,11 +152,13 @@ struct RouteLds {
 #define MFC_XY_WAVES32 5
 #endif
 // the routed variant's LDS (network, feature exchange) admits two workgroups per CU
-template <class T, bool ROUTE>
-constexpr int kXYWaves = ROUTE ? 2 : (sizeof(T) == 8 ? 3 : MFC_XY_WAVES32);
+// non-uniform cells keep the coefficient rows of the cell in registers: two
+// wavefronts per SIMD
+template <class T, bool ROUTE, bool STRETCH = false>
+constexpr int kXYWaves = ROUTE || STRETCH ? 2 : (sizeof(T) == 8 ? 3 : MFC_XY_WAVES32);
 
-template <class T, bool ROUTE, int ORDER>
-__global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE>))
+template <class T, bool ROUTE, int ORDER, bool STRETCH>
+__global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
     k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag,
          const float *__restrict__ mlpw, float logit_tau, T sqrt_eps, double *__restrict__ smax_partial)
 {
@@ -232,8 +234,15 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE>))
                     double Gam, Pi;
                     mixture<double>(g, double(w[6]), Gam, Pi);
                     const double cs = __builtin_sqrt(sound2<double>(Gam, Pi, double(w[0]) + double(w[1]), double(w[5])));
+                    if constexpr (STRETCH) {   // non-uniform cells: the largest (|u_d| + c)/dx_d
+                        const int ci[3] = {gx, gy, k};
 #pragma unroll
-                    for (int d = 0; d < 3; d++) smax = __builtin_fmax(smax, __builtin_fabs(double(w[2 + d])) + cs);
+                        for (int d = 0; d < 3; d++)
+                            smax = __builtin_fmax(smax, (__builtin_fabs(double(w[2 + d])) + cs) * inv_width(g, d, ci[d]));
+                    } else {
+#pragma unroll
+                        for (int d = 0; d < 3; d++) smax = __builtin_fmax(smax, __builtin_fabs(double(w[2 + d])) + cs);
+                    }
                 }
             }
             if (halo) {
@@ -262,10 +271,13 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE>))
                                                  logit_tau, lane);
             }
             if (valid) {
+                CoefRegs<T> cf;   // one row per cell for all seven variables
+                if constexpr (STRETCH && ORDER == 5) load_coefs<T>(coef_row(g, 0, x0 + c - 1), cf);
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     const T *st = &s_plane[v][row + NG][c];
                     if (ROUTE && lin) linear5_pair<T>(st[0], st[1], st[2], st[3], st[4], wP[v], s_minus[v][p]);
+                    else if (STRETCH && ORDER == 5) recon_cell<ORDER, T>(cf, st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
                     else recon_pair<ORDER, T>(st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
                 }
             }
@@ -285,7 +297,8 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE>))
             }
         }
         __syncthreads();
-        const T idx = T(g.inv_dx[0]), idy = T(g.inv_dx[1]);
+        const T idx = STRETCH ? T(inv_width(g, 0, gx)) : T(g.inv_dx[0]);
+        const T idy = STRETCH ? T(inv_width(g, 1, gy)) : T(g.inv_dx[1]);
         T L[NV], divu;
         if (cell) {
             const int f = ty * (TX + 2) + tx;
@@ -309,11 +322,16 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE>))
                                                  lane);
             }
             if (valid) {
+                CoefRegs<T> cf;
+                if constexpr (STRETCH && ORDER == 5) load_coefs<T>(coef_row(g, 1, y0 + r - 1), cf);
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     if (ROUTE && lin)
                         linear5_pair<T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
                                         s_plane[v][r + 3][li], s_plane[v][r + 4][li], wP[v], s_minus[v][p]);
+                    else if (STRETCH && ORDER == 5)
+                        recon_cell<ORDER, T>(cf, s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                             s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, wP[v], s_minus[v][p]);
                     else
                         recon_pair<ORDER, T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
                                    s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, wP[v], s_minus[v][p]);
@@ -403,7 +421,7 @@ constexpr int kRing = ROUTE ? MFC_Z_RING_ROUTE : MFC_Z_RING;
 static_assert(kRing<false> >= 1 && kRing<false> <= 4 && kRing<true> >= 1 && kRing<true> <= 4,
               "one to four planes in the ring");
 
-template <class T, bool ROUTE, int ORDER>
+template <class T, bool ROUTE, int ORDER, bool STRETCH>
 __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
     k_z(Grid g, const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ lxy, int mode, double dt,
         const double *__restrict__ dt_dev, int *__restrict__ flag, const float *__restrict__ mlpw, float logit_tau,
@@ -411,7 +429,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
 {
     constexpr int kRing = mfc::kRing<ROUTE>, kZReg = 5 - kRing;
     constexpr int NV = 7, A = 6, NZT = kZX * kZY;
-    const T eps = T(g.eps), idz = T(g.inv_dx[2]);
+    const T eps = T(g.eps), idz_u = T(g.inv_dx[2]);
     int bx, by, bz;
     tile_of_block(bx, by, bz);
     int gx = bx * kZX + threadIdx.x % kZX;
@@ -489,10 +507,13 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
             mlp::features<T>(av, rv, pv, sqrt_eps, f);
             lin = mlp::smooth_wave(s_mlp, scratch, f, logit_tau, lane);
         }
+        CoefRegs<T> cf;   // cell k+1 of this window
+        if constexpr (STRETCH && ORDER == 5) load_coefs<T>(coef_row(g, 2, k + 1), cf);
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             const T w0 = win(0, v), w1 = win(1, v), w2 = win(2, v), w3 = win(3, v), w4 = win(4, v);
             if (ROUTE && lin) linear5_pair<T>(w0, w1, w2, w3, w4, pn[v], mn[v]);
+            else if (STRETCH && ORDER == 5) recon_cell<ORDER, T>(cf, w0, w1, w2, w3, w4, eps, pn[v], mn[v]);
             else recon_pair<ORDER, T>(w0, w1, w2, w3, w4, eps, pn[v], mn[v]);
         }
         if (k >= z0 - 1) bad |= hllc<3, 2, T>(g, pk, mn, Fzn, Fzn[NV]);
@@ -500,6 +521,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
         for (int v = 0; v < NV; v++) pk[v] = pn[v];
         if (k >= z0 && own) {
             const int64_t c = offset(g, gx, gy, k);
+            const T idz = STRETCH ? T(inv_width(g, 2, k)) : idz_u;
             T L[NV], divu;
             if constexpr (kZEarly<T>) {
 #pragma unroll
@@ -552,7 +574,7 @@ dim3 xy_grid(const Grid &g)
     return dim3((g.n[0] + TX - 1) / TX, (g.n[1] + TY - 1) / TY, (g.n[2] + kPlanesXY - 1) / kPlanesXY);
 }
 
-template <class T, bool ROUTE, int ORDER>
+template <class T, bool ROUTE, int ORDER, bool STRETCH = false>
 int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s,
               double cfl)
 {
@@ -563,11 +585,11 @@ int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
     const T se = T(__builtin_sqrt(g.eps));
     double *partial = cfl > 0.0 ? h->partial : nullptr;
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_xy<T, ROUTE, ORDER>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se, partial);
+    hipLaunchKernelGGL((k_xy<T, ROUTE, ORDER, STRETCH>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se, partial);
     timing_end(h, s);
     if (partial) launch_step_begin(h, partial, (int)split_xy_blocks(g), cfl, 0.0, s);
     timing_begin(h, s, 1);
-    hipLaunchKernelGGL((k_z<T, ROUTE, ORDER>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag, h->mlp,
+    hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag, h->mlp,
                        h->logit_tau, se);
     timing_end(h, s, 1);
     return hip_status(hipGetLastError(), "split right-hand side launch");
@@ -592,6 +614,13 @@ int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int 
     float *fo = (float *)out;
     double *dout = (double *)out;
     const bool f32 = h->desc.precision == MFC_FP32_MIXED;
+    if (h->g.stretched) {   // non-uniform cells: WENO5 or first order (checked at init)
+        if (h->desc.recon == MFC_RECON_FIRST_ORDER)
+            return f32 ? rhs_split<float, false, 1, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                       : rhs_split<double, false, 1, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+        return f32 ? rhs_split<float, false, 5, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                   : rhs_split<double, false, 5, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+    }
     switch (h->desc.recon) {
     case MFC_RECON_LEARNED:
         return f32 ? rhs_split<float, true, 5>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)

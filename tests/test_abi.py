@@ -153,7 +153,8 @@ def test_learned_recon_rejected_for_staged(L):
 
 
 @pytest.mark.parametrize("kernel,recon,faces,code", [
-    (mfc.MFC_KERNEL_SPLIT, mfc.MFC_RECON_WENO5, "tanh", mfc.MFC_E_UNSUPPORTED),
+    (mfc.MFC_KERNEL_SPLIT, mfc.MFC_RECON_WENO3, "tanh", mfc.MFC_E_UNSUPPORTED),
+    (mfc.MFC_KERNEL_SPLIT, mfc.MFC_RECON_LEARNED, "tanh", mfc.MFC_E_UNSUPPORTED),
     (mfc.MFC_KERNEL_STAGED, mfc.MFC_RECON_WENO5, "tanh", mfc.MFC_E_UNSUPPORTED),
     (mfc.MFC_KERNEL_FUSED, mfc.MFC_RECON_WENO3, "tanh", mfc.MFC_E_UNSUPPORTED),
     (mfc.MFC_KERNEL_FUSED, mfc.MFC_RECON_LEARNED, "tanh", mfc.MFC_E_UNSUPPORTED),

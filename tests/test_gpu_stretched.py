@@ -1,7 +1,8 @@
-"""Non-uniform (tanh-stretched) cells on the GPU (fused kernel) against the
-oracle's non-uniform scheme: right-hand side and one step on 1D/2D/3D
-stretched grids for WENO5 and first order, multi-step runs, the CFL step
-size, and the FP32 form's error."""
+"""Non-uniform (tanh-stretched) cells on the GPU (fused kernel; split
+kernels in 3D) against the oracle's non-uniform scheme: right-hand side and
+one step on 1D/2D/3D stretched grids for WENO5 and first order, multi-step
+runs, the CFL step size, the FP32 form's error, and the split path's reading
+of boundary neighbours without ghost cells."""
 import dataclasses
 import sys
 
@@ -34,15 +35,17 @@ CASES = {
     "bubble_3d_17x15x17": lambda: W.bubble_collapse_3d(n=(17, 15, 17), stretch=0.6),
     "bubble_3d_x_only": lambda: with_faces(W.bubble_collapse_3d(n=(19, 16, 14)), (W.tanh_faces(19, depth=0.6), None, None)),
 }
-PAIRS = [(name, r) for name in CASES for r in sorted(RECON)]
+KERNELS = {"fused": mfc.MFC_KERNEL_FUSED, "split": mfc.MFC_KERNEL_SPLIT}
+PAIRS = [(name, r, k) for name in CASES for r in sorted(RECON) for k in sorted(KERNELS)
+         if k == "fused" or CASES[name]()[0].ndim == 3]
 
 
-@pytest.mark.parametrize("name,recon", PAIRS)
-def test_rhs_and_step(name, recon):
+@pytest.mark.parametrize("name,recon,kernel", PAIRS)
+def test_rhs_and_step(name, recon, kernel):
     spec, w = CASES[name]()
     rg, ro_kind = RECON[recon]
-    say(f"[stretched {recon}] {name}")
-    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_FUSED, recon=rg)
+    say(f"[stretched {recon} {kernel}] {name}")
+    s = mfc.Solver(spec, kernel=KERNELS[kernel], recon=rg)
     q = s.state_from_prim(w)
     s.fill_ghosts(q)
     r = s.rhs(q).cpu().numpy()
@@ -78,9 +81,10 @@ def test_sine_200_steps():
     assert err.max() <= 1e-10
 
 
-def test_bubble_20_steps():
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
+def test_bubble_20_steps(kernel):
     spec, w = W.bubble_collapse_3d(n=24, stretch=0.6)
-    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_FUSED)
+    s = mfc.Solver(spec, kernel=KERNELS[kernel])
     q = s.state_from_prim(w)
     s.run(q, 20, cfl=0.3)
     s.check()
@@ -92,9 +96,10 @@ def test_bubble_20_steps():
     assert err.max() <= 1e-10
 
 
-def test_max_wavespeed_is_the_inverse_cfl_time_scale():
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
+def test_max_wavespeed_is_the_inverse_cfl_time_scale(kernel):
     spec, w = W.bubble_collapse_3d(n=12, stretch=0.6)
-    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_FUSED)
+    s = mfc.Solver(spec, kernel=KERNELS[kernel])
     q = s.state_from_prim(w)
     sm = s.max_wavespeed(q)
     _, to, st = oracle.run(spec, oracle.prim_to_cons_field(spec, w), 1, cfl=1.0)
@@ -102,9 +107,10 @@ def test_max_wavespeed_is_the_inverse_cfl_time_scale():
     assert sm == pytest.approx(1.0 / to, rel=1e-13)
 
 
-def test_fp32_one_step():
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
+def test_fp32_one_step(kernel):
     spec, w = W.bubble_collapse_3d(n=(37, 21, 19), stretch=0.6)
-    s = mfc.Solver(spec, precision=mfc.MFC_FP32_MIXED, kernel=mfc.MFC_KERNEL_FUSED)
+    s = mfc.Solver(spec, precision=mfc.MFC_FP32_MIXED, kernel=KERNELS[kernel])
     q = s.state_from_prim(w)
     s.step(q, cfl=0.3)
     s.check()
@@ -117,3 +123,27 @@ def test_fp32_one_step():
     linf = rel_linf(got, qo, spec, floor_mom=acoustic_floor(spec, qi))
     say(f"[stretched fp32 1 step] rho L1 {rho_err:.2e}, rel Linf {linf.max():.2e}")
     assert rho_err <= 1e-6 and linf.max() <= 2e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_split_stretched_reads_no_ghost_cell(prec):
+    """Stretched cells on the split path with every ghost cell set to NaN:
+    the right-hand side and the step (with its CFL step size from the
+    non-uniform widths) are bitwise those of a filled state."""
+    import torch
+    spec, w = W.bubble_collapse_3d(n=(17, 15, 17), stretch=0.6)
+    spec = dataclasses.replace(spec, bc=(1, 1, 0, 0, 0, 0))
+    P = mfc.MFC_FP64 if prec == "fp64" else mfc.MFC_FP32_MIXED
+    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_SPLIT, precision=P)
+    q = s.state_from_prim(w)
+    s.fill_ghosts(q)
+    ghost = torch.ones(q.shape, dtype=torch.bool, device=q.device)
+    ghost[spec.interior] = False
+    qn = q.clone()
+    qn[ghost] = float("nan")
+    I = (slice(None),) + spec.interior[1:]
+    assert torch.equal(s.rhs(q)[I], s.rhs(qn)[I])
+    s.step(q, cfl=0.3)
+    s.step(qn, cfl=0.3)
+    s.check()
+    assert torch.equal(q[I], qn[I])
