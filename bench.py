@@ -240,8 +240,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: runs on one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the path runs on one GPU; sharding across GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

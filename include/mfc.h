@@ -54,7 +54,7 @@ enum {
     MFC_E_NOMEM = -2,        /* device allocation failed                              */
     MFC_E_HIP = -3,          /* a HIP runtime call or kernel launch failed            */
     MFC_E_NONPHYSICAL = -4,  /* a cell had rho <= 0, c^2 <= 0 or a non-finite value   */
-    MFC_E_UNSUPPORTED = -5   /* valid request this build does not implement          */
+    MFC_E_UNSUPPORTED = -5   /* valid request the library does not implement         */
 };
 
 /* Boundary condition per face.  EXTRAP: ghost cells copy the adjacent
