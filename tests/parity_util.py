@@ -1,5 +1,5 @@
-"""Error norms used by the parity tests (the reading of "relative L-infinity /
-L1" that the design notes record).
+"""Error norms used by the parity tests: this module's reading of "relative
+L-infinity / L1", stated below.
 
 States: per variable, the maximum (or sum) of |a - b| over interior cells
 divided by the same norm of the reference b.  The momentum components are
