@@ -31,24 +31,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RHS cell-updates/s (WENO5+HLLC), FP64 vs FP32/learned at fixed L1 error"
 
-# Algorithmic work per RHS cell-update, counted from the FP64 oracle's
-# formulation (every +, -, *, / and sqrt is one flop; material constants
-# precomputed; one reconstruction and one face per cell and direction):
-# conservative->primitive 28, WENO5 88 x 7 variables x 3 directions = 1848,
-# HLLC 146 x 3 = 438, flux differences + div(u) source 74, stage update 28.
-FLOPS_PER_CELL_UPDATE = 2416
+# Algorithmic work per cell-update: the oracle's operations counted by
+# running its source on a counting scalar type (tests/opcount; every +, -,
+# *, / and sqrt with a state-dependent operand is one flop, operations on
+# material and grid constants are not counted), asymptotic per interior cell
+# of a periodic box.  3D: 2641 per right-hand side (conservative->primitive
+# 28, per direction 870 = WENO5 99 x 7 + HLLC about 153 + flux differences and
+# div(u) 24, the div(u) source 2) plus the stage combination 28 (7 values of
+# 2, 5, 5 flops over the three stages).  2D: 1537 + 24.
+FLOPS_PER_CELL_UPDATE = 2669
+FLOPS_PER_CELL_UPDATE_2D = 1561
 # Bytes per cell-update of one fused pass, averaged over the three stages:
 # read the stage input (56 B), read q^n on stages 2 and 3 (56 B), write the
 # result (56 B): (112 + 168 + 168) / 3.
 BYTES_PER_CELL_UPDATE = (112 + 168 + 168) / 3
-# The split path's two kernels.  x+y kernel: conservative->primitive 28,
-# WENO5 88 x 7 x 2 = 1232, HLLC 146 x 2 = 292, x+y flux differences and
-# divergence 49 -> 1601 flops; reads the stage input (56 B) and writes the
-# x+y part (8 values, 64 B).  z kernel: the remaining 2416 - 1601 = 815 flops;
+# The split path's two kernels.  x+y kernel: conservative->primitive 28 and
+# two directions of 870 -> 1769 flops; reads the stage input (56 B) and
+# writes the x+y part (8 values, 64 B).  z kernel: the remaining
+# 2669 - 1769 = 900 flops (one direction, the source, the stage update);
 # reads the stage input, the x+y part and q^n on stages 2-3, writes the
 # result: 56 + 64 + 56 * 2/3 + 56 B.
-SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences)", flops=1601, bytes=56 + 64),
-         1: dict(name="k_z (z reconstruction, HLLC, source, stage update)", flops=2416 - 1601,
+SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences)", flops=1769, bytes=56 + 64),
+         1: dict(name="k_z (z reconstruction, HLLC, source, stage update)", flops=2669 - 1769,
                  bytes=56 + 64 + 56 * 2 / 3 + 56)}
 # Measured HBM traffic per launch (bytes) of the split path's kernels on the
 # 128^3 bubble: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each
@@ -183,11 +187,10 @@ def bench_ensemble(args, torch, mfc, W):
         s.run(q, args.steps, cfl=cfl)
     torch.cuda.synchronize()
     seq = time.perf_counter() - t0
-    # 2D algorithmic work per cell-update: conservative->primitive 28, WENO5
-    # 88 x 6 variables x 2 directions, HLLC 146 x 2, flux differences and
-    # divergence 49, stage update 28.  Bytes (FP32, 6 values of 4 B): read the
-    # stage input, read q^n on stages 2-3, write the result.
-    flops = 28 + 88 * 6 * 2 + 146 * 2 + 49 + 28
+    # 2D algorithmic work per cell-update (counted on the oracle, above).
+    # Bytes (FP32, 6 values of 4 B): read the stage input, read q^n on
+    # stages 2-3, write the result.
+    flops = FLOPS_PER_CELL_UPDATE_2D
     nbytes = (2 * 24 + 3 * 24 + 3 * 24) / 3
     bound = "alu" if flops / nbytes > PEAK_FP32_VALU / PEAK_HBM else "hbm"
     ach = flops * b.cells / avg
