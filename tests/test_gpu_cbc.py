@@ -45,7 +45,35 @@ CASES = {
     "supersonic_3d_-": lambda: with_bc(W.supersonic_periodic(3, 12, sign=-1.0), ALL),
     "bubble_3d": lambda: with_bc(W.bubble_collapse_3d(n=(17, 15, 17)), ALL),
     "droplet_2d": lambda: with_bc(W.droplet_shock_2d((17, 17), W.SEED + 21), ALL),
+    # many boundary-pass blocks per face, ragged tiles
+    "smooth_3d_66x53x40": lambda: with_bc(_smooth_box((66, 53, 40)), ALL),
 }
+
+
+def _smooth_box(n):
+    spec, w = W.random_smooth_periodic(3, 8)
+    spec = dataclasses.replace(spec, n=n, hi=tuple(float(v) / 64 for v in n))
+    return spec, _resample(spec)
+
+
+def _resample(spec):
+    # the smooth field of random_smooth_periodic evaluated on this grid's cells
+    import math
+    rng = np.random.default_rng(W.SEED + 91)
+    coords = spec.mesh()
+    shape = spec.shape[1:]
+
+    def field():
+        f = np.zeros(shape)
+        for _ in range(3):
+            k = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0, 2 * math.pi)
+            f = f + rng.uniform(0.2, 1.0) * np.sin(ph + sum(2 * math.pi * k[d] * coords[d] for d in range(3)))
+        return f / 3
+
+    a = 0.5 + 0.2 * field()
+    return W._assemble(spec, a, 1000.0 * (1.0 + 0.01 * field()), 1.2 * (1.0 + 0.1 * field()),
+                       [10.0 * field() for _ in range(3)], 1.0e5 * (1.0 + 0.3 * field()))
 
 
 def kernels_for(spec):

@@ -34,6 +34,8 @@ CASES = {
                                            (W.tanh_faces(40, centre=0.4, depth=0.5), W.tanh_faces(33, depth=0.3), None)),
     "bubble_3d_17x15x17": lambda: W.bubble_collapse_3d(n=(17, 15, 17), stretch=0.6),
     "bubble_3d_x_only": lambda: with_faces(W.bubble_collapse_3d(n=(19, 16, 14)), (W.tanh_faces(19, depth=0.6), None, None)),
+    # several x+y tiles and z chunks in every direction, ragged in x and y
+    "bubble_3d_66x53x64": lambda: W.bubble_collapse_3d(n=(66, 53, 64), stretch=0.6),
 }
 KERNELS = {"fused": mfc.MFC_KERNEL_FUSED, "split": mfc.MFC_KERNEL_SPLIT}
 PAIRS = [(name, r, k) for name in CASES for r in sorted(RECON) for k in sorted(KERNELS)
