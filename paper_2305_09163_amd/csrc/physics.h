@@ -180,10 +180,11 @@ __device__ __forceinline__ T alpha_source(const Grid &g, T alpha1, T p)
 // d = vp2 - vp1 and the smoothness indicators.
 //
 // Arithmetic, equal to the Jiang-Shu definitions up to rounding:
-//   - every smoothness indicator is scaled by 3, with eps scaled alike
-//     (3 beta_0 = a (10a - 11b) + 4b^2, 3 beta_1 = c (4c - 5a) + 4a^2,
-//     3 beta_2 = c (10c - 11d) + 4d^2); the weights depend only on ratios of
-//     (eps + beta_r)^2, so the common factor cancels;
+//   - every smoothness indicator is scaled by 3/4, with eps scaled alike
+//     (3/4 beta_0 = a (2.5a - 2.75b) + b^2, 3/4 beta_1 = c (c - 1.25a) + a^2,
+//     3/4 beta_2 = c (2.5c - 2.75d) + d^2: no product by a constant is left
+//     in the squares); the weights depend only on ratios of (eps + beta_r)^2,
+//     so the common factor cancels;
 //   - the candidates enter as increments over v0 scaled by 6
 //     (6 (p_r - v0) at x_{i+1/2}: 5a - 2b, 2c + a, 4c - d; at x_{i-1/2}:
 //     b - 4a, -(2a + c), 2d - 5c), which reproduces constants exactly.
@@ -198,10 +199,10 @@ __device__ __forceinline__ void weno5_pair(double vm2, double vm1, double v0, do
                                            double eps, double &plus, double &minus)
 {
     const double b = vm1 - vm2, a = v0 - vm1, c = vp1 - v0, d = vp2 - vp1;
-    const double e3 = 3.0 * eps;
-    const double e0 = __builtin_fma(a, __builtin_fma(10.0, a, -11.0 * b), __builtin_fma(4.0 * b, b, e3));
-    const double e1 = __builtin_fma(c, __builtin_fma(4.0, c, -5.0 * a), __builtin_fma(4.0 * a, a, e3));
-    const double e2 = __builtin_fma(c, __builtin_fma(10.0, c, -11.0 * d), __builtin_fma(4.0 * d, d, e3));
+    const double e3 = 0.75 * eps;
+    const double e0 = __builtin_fma(a, __builtin_fma(2.5, a, -2.75 * b), __builtin_fma(b, b, e3));
+    const double e1 = __builtin_fma(c, __builtin_fma(-1.25, a, c), __builtin_fma(a, a, e3));
+    const double e2 = __builtin_fma(c, __builtin_fma(2.5, c, -2.75 * d), __builtin_fma(d, d, e3));
     const double s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
     const double m0 = s1 * s2, m1 = 6.0 * (s0 * s2), m2 = s0 * s1;  // m1 carries the ideal weight 6
     const double sp = __builtin_fma(3.0, m2, m0 + m1);                // weights 1, 6, 3
@@ -219,10 +220,10 @@ __device__ __forceinline__ void weno5_pair(float vm2, float vm1, float v0, float
                                            float &plus, float &minus)
 {
     const float b = vm1 - vm2, a = v0 - vm1, c = vp1 - v0, d = vp2 - vp1;
-    const float e3 = 3.0f * eps;
-    const float e0 = __builtin_fmaf(a, __builtin_fmaf(10.0f, a, -11.0f * b), __builtin_fmaf(4.0f * b, b, e3));
-    const float e1 = __builtin_fmaf(c, __builtin_fmaf(4.0f, c, -5.0f * a), __builtin_fmaf(4.0f * a, a, e3));
-    const float e2 = __builtin_fmaf(c, __builtin_fmaf(10.0f, c, -11.0f * d), __builtin_fmaf(4.0f * d, d, e3));
+    const float e3 = 0.75f * eps;
+    const float e0 = __builtin_fmaf(a, __builtin_fmaf(2.5f, a, -2.75f * b), __builtin_fmaf(b, b, e3));
+    const float e1 = __builtin_fmaf(c, __builtin_fmaf(-1.25f, a, c), __builtin_fmaf(a, a, e3));
+    const float e2 = __builtin_fmaf(c, __builtin_fmaf(2.5f, c, -2.75f * d), __builtin_fmaf(d, d, e3));
     const float emin = __builtin_fminf(e0, __builtin_fminf(e1, e2));
     const float t0 = emin * rcp(e0), t1 = emin * rcp(e1), t2 = emin * rcp(e2);
     const float m0 = t0 * t0, m1 = 6.0f * (t1 * t1), m2 = t2 * t2;
