@@ -85,12 +85,14 @@ __device__ __forceinline__ double fmaxT(double a, double b) { return __builtin_f
 __device__ __forceinline__ float fmaxT(float a, float b) { return __builtin_fmaxf(a, b); }
 
 // ------------------------------------------------------------------- EOS
+// Gamma and Pi of the mixture, affine in alpha1 (alpha2 = 1 - alpha1):
+// Gamma = g2 + alpha1 (g1 - g2), Pi = h2 + alpha1 (h1 - h2), one FMA each
+// (the differences are constants of the grid).
 template <class T>
 __device__ __forceinline__ void mixture(const Grid &g, T a1, T &Gam, T &Pi)
 {
-    T a2 = T(1) - a1;
-    Gam = a1 * T(g.g1) + a2 * T(g.g2);
-    Pi = a1 * T(g.h1) + a2 * T(g.h2);
+    Gam = fmaT(a1, T(g.g1 - g.g2), T(g.g2));
+    Pi = fmaT(a1, T(g.h1 - g.h2), T(g.h2));
 }
 
 // Frozen mixture sound speed squared, c^2 = ((Gamma + 1) p + Pi) / (Gamma rho).
