@@ -465,10 +465,11 @@ __device__ __forceinline__ bool hllc(const Grid &g, const T *wL, const T *wR, T 
     const T En = Gam * p + Pi + T(0.5) * rho * u2;
 
     // physical flux of that side
+    const T mn = rho * un;   // normal mass flux
     F[0] = w[0] * un;
     F[1] = w[1] * un;
 #pragma unroll
-    for (int m = 0; m < NDIM; m++) F[2 + m] = rho * w[2 + m] * un + (m == DIR ? p : T(0));
+    for (int m = 0; m < NDIM; m++) F[2 + m] = (m == DIR) ? fmaT(mn, un, p) : mn * w[2 + m];
     F[E] = (En + p) * un;
 
     // star correction s_K (q*_K - q_K), with xi - 1 = (s* - u)/(s_K - s*)
@@ -476,10 +477,11 @@ __device__ __forceinline__ bool hllc(const Grid &g, const T *wL, const T *wR, T 
     const T xim1 = (sS - un) * ism;
     const T xi = (sK - un) * ism;
     T dq[NV - 1];
+    const T xr = xim1 * rho;
     dq[0] = xim1 * w[0];
     dq[1] = xim1 * w[1];
 #pragma unroll
-    for (int m = 0; m < NDIM; m++) dq[2 + m] = (m == DIR) ? rho * (xi * sS - un) : xim1 * rho * w[2 + m];
+    for (int m = 0; m < NDIM; m++) dq[2 + m] = (m == DIR) ? rho * fmaT(xi, sS, -un) : xr * w[2 + m];
     // xi (s* - u)(rho s* + p/(s_K - u)) = (s* - u)(xi rho s* + p/(s_K - s*))
     dq[E] = xim1 * En + (sS - un) * fmaT(xi * rho, sS, p * ism);
 #pragma unroll
