@@ -199,9 +199,11 @@ int mfc_check(mfc_grid *g, void *stream);
  * is bracketed by HIP events on the launch stream.  Slot 0 is the main
  * right-hand-side kernel (the fused kernel, the x+y kernel of the split
  * path, or the whole staged sequence); slot 1 is the z + stage-update kernel
- * of the split path.  mfc_kernel_time synchronises, returns the summed
- * duration (ms) and number of launches of that slot since the last call for
- * it, and resets them.  slot outside [0, 1] gives MFC_E_ARG. */
+ * of the split path.  Disabling stops the recording and keeps what was
+ * recorded, so timing can cover a sample of the launches (say every tenth
+ * step).  mfc_kernel_time synchronises, returns the summed duration (ms) and
+ * number of timed launches of that slot since the last call for it, and
+ * resets them.  slot outside [0, 1] gives MFC_E_ARG. */
 int mfc_set_kernel_timing(mfc_grid *g, int enable);
 int mfc_kernel_time(mfc_grid *g, int slot, double *ms_total, int64_t *launches);
 

@@ -680,8 +680,7 @@ int mfc_check(mfc_grid *h, void *stream)
 int mfc_set_kernel_timing(mfc_grid *h, int enable)
 {
     if (bad_handle(h)) return fail(MFC_E_ARG, "handle is NULL");
-    h->timing = enable != 0;
-    h->ev_used[0] = h->ev_used[1] = 0;
+    h->timing = enable != 0;   // what was recorded stays until mfc_kernel_time reads it
     return MFC_OK;
 }
 
