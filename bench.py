@@ -54,18 +54,20 @@ BYTES_PER_CELL_UPDATE = (112 + 168 + 168) / 3
 SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences)", flops=1769, bytes=56 + 64),
          1: dict(name="k_z (z reconstruction, HLLC, source, stage update)", flops=2669 - 1769,
                  bytes=56 + 64 + 56 * 2 / 3 + 56)}
+# The library's kernel events bracket the launches of every tenth step of
+# the timed region.
+KERNEL_TIMING_STRIDE = 10
 # Measured HBM traffic per launch (bytes) of the split path's kernels on the
 # 128^3 bubble: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each
 # scaled by its reading for a copy kernel of known size (FETCH_SIZE x 2.00,
 # WRITE_SIZE x 1.00).  Valid only for the kernel sources they were taken on;
 # any change to those files turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h")
-TRAFFIC = {"sha256": "0923ec767935bff9bc8972ba97f15e7df1ba0b65cd99fa77e30208ad507158b2",
-           ("split", "fp32", 128, 0): (61.78e6, 70.32e6),
-           ("split", "fp32", 128, 1): (245.75e6, 62.37e6),
-           ("split", "fp64", 128, 0): (124.79e6, 139.51e6),
-           ("split", "fp64", 128, 1): (514.99e6, 124.15e6)}
-KERNEL_TIMING_STRIDE = 10
+TRAFFIC = {"sha256": "f6604d396a8fe909ea12d48b7fdfd32b55845297aaa533b2acac3acd5a8fb752",
+           ("split", "fp32", 128, 0): (61.76e6, 70.33e6),
+           ("split", "fp32", 128, 1): (245.80e6, 62.57e6),
+           ("split", "fp64", 128, 0): (124.82e6, 139.55e6),
+           ("split", "fp64", 128, 1): (515.78e6, 124.21e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
