@@ -127,7 +127,9 @@ __device__ __forceinline__ bool cons_to_prim(const Grid &g, const T *q, T *w)
     for (int m = 0; m < NDIM; m++) ke += double(q[2 + m]) * double(w[2 + m]);
     double Gam, Pi;
     mixture<double>(g, double(q[A]), Gam, Pi);
-    const double iG = rcp(Gam);
+    // the FP32 form stores p as float: the hardware estimate of 1/Gamma
+    // (about 24 correct bits) is as accurate as that rounding
+    const double iG = std::is_same<T, float>::value ? __builtin_amdgcn_rcp(Gam) : rcp(Gam);
     const double p = (double(q[E]) - 0.5 * ke - Pi) * iG;
     w[E] = T(p);
     // c^2 = ((Gamma + 1) p + Pi) / (Gamma rho): its sign and finiteness
@@ -416,7 +418,8 @@ __device__ __forceinline__ T contact_speed(T pL, T pR, T mL, T mR, T uL, T uR)
         return (pR - pL + mL * uL - mR * uR) * rcp(mL - mR);
     } else {
         const double num = double(pR) - double(pL) + double(mL) * double(uL) - double(mR) * double(uR);
-        return T(num * rcp(double(mL) - double(mR)));
+        // rounded to float: the estimate of the reciprocal (about 24 bits) suffices
+        return T(num * __builtin_amdgcn_rcp(double(mL) - double(mR)));
     }
 }
 
