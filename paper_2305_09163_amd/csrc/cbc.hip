@@ -55,7 +55,10 @@ __device__ constexpr int at(int o)
 // Change of the stage derivative of boundary cell c (c[D] = its boundary
 // index) from the characteristic face SIDE of dimension D: the
 // characteristic rate minus the finite-volume terms normal to the face.
-template <int NDIM, int D, int SIDE, class T, int ORDER>
+// STORED: those terms were kept by the split stage kernels (Grid::cbc_fv);
+// otherwise they are recomputed here, the cell's two normal fluxes on the
+// two lanes of a pair.
+template <int NDIM, int D, int SIDE, class T, int ORDER, bool STORED>
 __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__restrict__ q, T delta[4 + NDIM],
                                            int half)
 {
@@ -68,7 +71,7 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
 
     T W[4][NV];
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
+    for (int k = 0; k < (STORED ? 3 : 4); k++) {   // the stored terms need only the one-sided stencil
         c[D] = min(max(b + k * sg, 0), n - 1);   // n = 3: the third neighbour is clamped
         const int64_t off = (int64_t)(c[2] + g.off[2]) * g.stride[2] + (int64_t)(c[1] + g.off[1]) * g.stride[1] +
                             (c[0] + g.off[0]);
@@ -79,6 +82,15 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
     }
     c[D] = b;
 
+    T fv[NV];
+    if constexpr (STORED) {
+        constexpr int F = 2 * D + SIDE;
+        const int c1 = D == 0 ? c[1] : c[0], n1 = D == 0 ? g.n[1] : g.n[0], c2 = D == 2 ? c[1] : c[2];
+        const T *src = (const T *)g.cbc_fv + g.cbc_off[F] + 8 * ((int64_t)c1 + (int64_t)n1 * c2);
+#pragma unroll
+        for (int v = 0; v < NV; v++) fv[v] = src[v];
+        fv[A] += W[0][A] * src[7];   // the normal part of alpha1 div(u)
+    } else {
     // finite-volume terms normal to the face.  The two lanes of a pair
     // compute one flux each on the same instruction stream, lane 0 the flux
     // at b-1/2 (left state: cell b-1 reconstructed from stencil cells 0..4,
@@ -96,7 +108,6 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
     }
     T F[NV], uf;
     bad |= hllc<NDIM, D, T>(g, lft, rgt, F, uf);
-    T fv[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) {
         const T other = __shfl_xor(F[v], 1);
@@ -104,6 +115,7 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
     }
     const T uother = __shfl_xor(uf, 1);
     fv[A] += W[0][A] * ((half ? uf - uother : uother - uf) * idx);
+    }
 
     // characteristic form on the boundary cell: second-order one-sided
     // differences into the domain
@@ -146,19 +158,19 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
     return bad;
 }
 
-// Two lanes per (characteristic face, boundary cell of it).  A cell on
-// several characteristic faces (an edge or corner) belongs to the first of
-// them, whose lane pair adds the changes of all of them in face order: every
-// cell is written by one lane, once, in a fixed order.
-template <int NDIM, class T, int ORDER>
+// One lane (STORED) or two lanes per (characteristic face, boundary cell of
+// it).  A cell on several characteristic faces (an edge or corner) belongs
+// to the first of them, whose lanes add the changes of all of them in face
+// order: every cell is written by one lane, once, in a fixed order.
+template <int NDIM, class T, int ORDER, bool STORED>
 __global__ void __launch_bounds__(kCbcThreads, MFC_CBC_WAVES)
     k_cbc(Grid g, CbcFaces F, const T *__restrict__ q, T *out, int mode, double dt, const double *__restrict__ dt_dev,
           int *__restrict__ flag)
 {
     constexpr int NV = 4 + NDIM;
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t t = gt >> 1;   // the cell; both lanes of a pair leave or stay together
-    const int half = (int)(gt & 1);
+    const int64_t t = STORED ? gt : gt >> 1;   // the cell; both lanes of a pair leave or stay together
+    const int half = STORED ? 1 : (int)(gt & 1);
     if (t >= F.start[6]) return;
     int my = -1;
     int64_t first = 0;
@@ -189,15 +201,15 @@ __global__ void __launch_bounds__(kCbcThreads, MFC_CBC_WAVES)
 #pragma unroll
     for (int v = 0; v < NV; v++) delta[v] = T(0);
     bool bad = false;
-    if (on & 1) bad |= face_delta<NDIM, 0, 0, T, ORDER>(g, c, q, delta, half);
-    if (on & 2) bad |= face_delta<NDIM, 0, 1, T, ORDER>(g, c, q, delta, half);
+    if (on & 1) bad |= face_delta<NDIM, 0, 0, T, ORDER, STORED>(g, c, q, delta, half);
+    if (on & 2) bad |= face_delta<NDIM, 0, 1, T, ORDER, STORED>(g, c, q, delta, half);
     if constexpr (NDIM >= 2) {
-        if (on & 4) bad |= face_delta<NDIM, 1, 0, T, ORDER>(g, c, q, delta, half);
-        if (on & 8) bad |= face_delta<NDIM, 1, 1, T, ORDER>(g, c, q, delta, half);
+        if (on & 4) bad |= face_delta<NDIM, 1, 0, T, ORDER, STORED>(g, c, q, delta, half);
+        if (on & 8) bad |= face_delta<NDIM, 1, 1, T, ORDER, STORED>(g, c, q, delta, half);
     }
     if constexpr (NDIM == 3) {
-        if (on & 16) bad |= face_delta<NDIM, 2, 0, T, ORDER>(g, c, q, delta, half);
-        if (on & 32) bad |= face_delta<NDIM, 2, 1, T, ORDER>(g, c, q, delta, half);
+        if (on & 16) bad |= face_delta<NDIM, 2, 0, T, ORDER, STORED>(g, c, q, delta, half);
+        if (on & 32) bad |= face_delta<NDIM, 2, 1, T, ORDER, STORED>(g, c, q, delta, half);
     }
 
     const int64_t off = (int64_t)(c[2] + g.off[2]) * g.stride[2] + (int64_t)(c[1] + g.off[1]) * g.stride[1] +
@@ -226,18 +238,28 @@ void launch_t(mfc_grid *h, const void *q, void *out, int mode, double dt, const 
     }
     F.start[6] = total;
     if (F.mask == 0) return;
-    const dim3 grid((unsigned)((2 * total + kCbcThreads - 1) / kCbcThreads));
+    // the split path (3D) keeps the normal terms; the others recompute them
+    const bool stored = g.cbc_mask != 0;
+    const int lanes = stored ? 1 : 2;
+    const dim3 grid((unsigned)((lanes * total + kCbcThreads - 1) / kCbcThreads));
     const T *a = (const T *)q;
     T *o = (T *)out;
     switch (g.ndim) {
     case 1:
-        hipLaunchKernelGGL((k_cbc<1, T, ORDER>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev, h->flag);
+        hipLaunchKernelGGL((k_cbc<1, T, ORDER, false>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev,
+                           h->flag);
         break;
     case 2:
-        hipLaunchKernelGGL((k_cbc<2, T, ORDER>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev, h->flag);
+        hipLaunchKernelGGL((k_cbc<2, T, ORDER, false>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev,
+                           h->flag);
         break;
     default:
-        hipLaunchKernelGGL((k_cbc<3, T, ORDER>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev, h->flag);
+        if (stored)
+            hipLaunchKernelGGL((k_cbc<3, T, ORDER, true>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt,
+                               dt_dev, h->flag);
+        else
+            hipLaunchKernelGGL((k_cbc<3, T, ORDER, false>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt,
+                               dt_dev, h->flag);
     }
 }
 

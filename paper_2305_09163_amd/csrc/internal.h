@@ -28,6 +28,7 @@ struct mfc_grid {
     double *recm = nullptr;    // staged path: reconstruction at x_{i-1/2}, per cell
     double *faces = nullptr;   // staged path: 3 directions x (nvar + 1) face arrays
     double *lxy = nullptr;     // split path: x+y flux differences and div(u), nvar + 1 arrays
+    void *cbc_fv = nullptr;    // split path: normal terms of characteristic boundary cells
     double *partial = nullptr; // per-block maxima of the wave-speed reduction
     int64_t partial_len = 0;   // its length (the larger of the two producers' grids)
     double *scalars = nullptr; // [0] smax, [1] dt, [2] t, [3] spare

@@ -400,7 +400,7 @@ int mfc_free_grid(mfc_grid *h)
     (void)hipDeviceSynchronize();
     for (void *p : {(void *)h->stage_a, (void *)h->stage_b, (void *)h->prim, (void *)h->recp, (void *)h->recm,
                     (void *)h->faces, (void *)h->lxy, (void *)h->partial, (void *)h->scalars, (void *)h->flag,
-                    (void *)h->mlp})
+                    (void *)h->mlp, h->cbc_fv})
         if (p) (void)hipFree(p);
     for (auto &ev : h->ev)
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -477,8 +477,21 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
         alloc((void **)&h->recm, sb);
         alloc((void **)&h->faces, (int64_t)3 * (h->nvar + 1) * h->cells_padded * 8);
     }
-    if (desc->kernel == MFC_KERNEL_SPLIT)
+    if (desc->kernel == MFC_KERNEL_SPLIT) {
         alloc((void **)&h->lxy, (int64_t)(h->nvar + 1) * h->cells_padded * elem_bytes(h));
+        // characteristic faces: the stage kernels keep the boundary cells'
+        // normal terms (8 values per cell and face) for the boundary pass
+        int64_t words = 0;
+        for (int f = 0; f < 2 * g.ndim; f++) {
+            if (g.bc[f] != MFC_BC_CHARACTERISTIC) continue;
+            const int d = f >> 1;
+            g.cbc_mask |= 1 << f;
+            g.cbc_off[f] = words;
+            words += 8 * (int64_t)(d == 0 ? g.n[1] : g.n[0]) * (d == 2 ? g.n[1] : g.n[2]);
+        }
+        if (words) alloc(&h->cbc_fv, words * elem_bytes(h));
+        g.cbc_fv = h->cbc_fv;
+    }
     h->partial_len = std::max<int64_t>(kReduceBlocks, desc->ndim == 3 ? split_xy_blocks(g) : 0);
     alloc((void **)&h->partial, h->partial_len * 8);
     alloc((void **)&h->scalars, 4 * 8);

@@ -46,8 +46,28 @@ struct Grid {
     int stretched;
     const double *wcoef[3];
     const double *winv[3];
+    // characteristic faces on the split path: bit f of cbc_mask marks face f
+    // (x-, x+, y-, y+, z-, z+); the stage kernels store the finite-volume
+    // terms normal to it of its boundary cells (7 flux differences, then the
+    // normal part of div(u)) at cbc_fv + cbc_off[f] + 8 (c1 + n1 c2), in the
+    // storage type, where c1 < n1 and c2 are the cell's two other
+    // coordinates, the lower dimension first
+    int cbc_mask;
+    void *cbc_fv;
+    int64_t cbc_off[6];
 };
 constexpr int kStretchCoef = 42;
+
+// Store the normal finite-volume terms of a boundary cell of characteristic
+// face F (the split kernels; read back by the boundary post-pass).
+template <int F, class T>
+__device__ __forceinline__ void store_normal_terms(const Grid &g, int c1, int n1, int c2, const T *L, T divu)
+{
+    T *dst = (T *)g.cbc_fv + g.cbc_off[F] + 8 * ((int64_t)c1 + (int64_t)n1 * c2);
+#pragma unroll
+    for (int v = 0; v < 7; v++) dst[v] = L[v];
+    dst[7] = divu;
+}
 
 // ---------------------------------------------------------------- reciprocal
 // Double reciprocal: the hardware estimate (about 24 correct bits) refined by

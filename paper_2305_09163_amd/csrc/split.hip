@@ -157,7 +157,7 @@ struct RouteLds {
 template <class T, bool ROUTE, bool STRETCH = false>
 constexpr int kXYWaves = ROUTE || STRETCH ? 2 : (sizeof(T) == 8 ? 3 : MFC_XY_WAVES32);
 
-template <class T, bool ROUTE, int ORDER, bool STRETCH>
+template <class T, bool ROUTE, int ORDER, bool STRETCH, bool KEEP>
 __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
     k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag,
          const float *__restrict__ mlpw, float logit_tau, T sqrt_eps, double *__restrict__ smax_partial)
@@ -305,6 +305,10 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
 #pragma unroll
             for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * idx;
             divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * idx;
+            if (KEEP && (g.cbc_mask & 3)) {   // characteristic x faces keep the boundary cells' x terms
+                if (own && gx == 0 && (g.cbc_mask & 1)) store_normal_terms<0, T>(g, gy, g.n[1], k, L, divu);
+                if (own && gx == g.n[0] - 1 && (g.cbc_mask & 2)) store_normal_terms<1, T>(g, gy, g.n[1], k, L, divu);
+            }
         }
         // ---- y: thread p reconstructs row p / TX - 1 of column p % TX and
         // solves the face on its + side
@@ -355,6 +359,14 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
         __syncthreads();
         if (cell) {
             const int f = ty * TX + tx;
+            if (KEEP && (g.cbc_mask & 12)) {   // characteristic y faces keep the boundary cells' y terms
+                T Ly[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++) Ly[v] = (s_flux[v][f] - s_flux[v][f + TX]) * idy;
+                const T dy = (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
+                if (own && gy == 0 && (g.cbc_mask & 4)) store_normal_terms<2, T>(g, gx, g.n[0], k, Ly, dy);
+                if (own && gy == g.n[1] - 1 && (g.cbc_mask & 8)) store_normal_terms<3, T>(g, gx, g.n[0], k, Ly, dy);
+            }
 #pragma unroll
             for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * idy;
             divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
@@ -421,7 +433,7 @@ constexpr int kRing = ROUTE ? MFC_Z_RING_ROUTE : MFC_Z_RING;
 static_assert(kRing<false> >= 1 && kRing<false> <= 4 && kRing<true> >= 1 && kRing<true> <= 4,
               "one to four planes in the ring");
 
-template <class T, bool ROUTE, int ORDER, bool STRETCH>
+template <class T, bool ROUTE, int ORDER, bool STRETCH, bool KEEP>
 __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
     k_z(Grid g, const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ lxy, int mode, double dt,
         const double *__restrict__ dt_dev, int *__restrict__ flag, const float *__restrict__ mlpw, float logit_tau,
@@ -523,6 +535,14 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
             const int64_t c = offset(g, gx, gy, k);
             const T idz = STRETCH ? T(inv_width(g, 2, k)) : idz_u;
             T L[NV], divu;
+            if (KEEP && (g.cbc_mask & 48)) {   // characteristic z faces keep the boundary cells' z terms
+                T Lz[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++) Lz[v] = (Fz[v] - Fzn[v]) * idz;
+                const T dz = (Fzn[NV] - Fz[NV]) * idz;
+                if (k == 0 && (g.cbc_mask & 16)) store_normal_terms<4, T>(g, gx, g.n[0], gy, Lz, dz);
+                if (k == g.n[2] - 1 && (g.cbc_mask & 32)) store_normal_terms<5, T>(g, gx, g.n[0], gy, Lz, dz);
+            }
             if constexpr (kZEarly<T>) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) L[v] = lx[v] + (Fz[v] - Fzn[v]) * idz;
@@ -576,7 +596,7 @@ dim3 xy_grid(const Grid &g)
     return dim3((g.n[0] + TX - 1) / TX, (g.n[1] + TY - 1) / TY, (g.n[2] + kPlanesXY - 1) / kPlanesXY);
 }
 
-template <class T, bool ROUTE, int ORDER, bool STRETCH = false>
+template <class T, bool ROUTE, int ORDER, bool STRETCH = false, bool KEEP = false>
 int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s,
               double cfl)
 {
@@ -587,11 +607,11 @@ int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
     const T se = T(__builtin_sqrt(g.eps));
     double *partial = cfl > 0.0 ? h->partial : nullptr;
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_xy<T, ROUTE, ORDER, STRETCH>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se, partial);
+    hipLaunchKernelGGL((k_xy<T, ROUTE, ORDER, STRETCH, KEEP>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se, partial);
     timing_end(h, s);
     if (partial) launch_step_begin(h, partial, (int)split_xy_blocks(g), cfl, 0.0, s);
     timing_begin(h, s, 1);
-    hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag, h->mlp,
+    hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH, KEEP>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag, h->mlp,
                        h->logit_tau, se);
     timing_end(h, s, 1);
     return hip_status(hipGetLastError(), "split right-hand side launch");
@@ -622,6 +642,16 @@ int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int 
                        : rhs_split<double, false, 1, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
         return f32 ? rhs_split<float, false, 5, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
                    : rhs_split<double, false, 5, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+    }
+    if (h->g.cbc_mask) {   // characteristic faces (WENO5, WENO3 or first order; checked at init)
+        if (h->desc.recon == MFC_RECON_WENO3)
+            return f32 ? rhs_split<float, false, 3, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                       : rhs_split<double, false, 3, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+        if (h->desc.recon == MFC_RECON_FIRST_ORDER)
+            return f32 ? rhs_split<float, false, 1, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                       : rhs_split<double, false, 1, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+        return f32 ? rhs_split<float, false, 5, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                   : rhs_split<double, false, 5, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
     }
     switch (h->desc.recon) {
     case MFC_RECON_LEARNED:
