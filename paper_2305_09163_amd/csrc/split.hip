@@ -499,7 +499,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
                 if (mode != 0) {
 #pragma unroll
                     for (int v = 0; v < NV; v++) {
-                        if (mode != 1) qa[v] = q0[v * g.vstride + c];   // stage 1: ca = 0
+                        qa[v] = q0[v * g.vstride + c];
                         qb[v] = q[v * g.vstride + c];
                     }
                 }
@@ -568,9 +568,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
                     }
                 }
 #pragma unroll
-                for (int v = 0; v < NV; v++)
-                    out[v * g.vstride + c] = (kZEarly<T> && mode == 1) ? qb[v] + hdt * L[v]   // qa not loaded
-                                                                       : ca * qa[v] + cb * (qb[v] + hdt * L[v]);
+                for (int v = 0; v < NV; v++) out[v * g.vstride + c] = ca * qa[v] + cb * (qb[v] + hdt * L[v]);
             }
         }
 #pragma unroll
