@@ -63,11 +63,11 @@ KERNEL_TIMING_STRIDE = 10
 # WRITE_SIZE x 1.00).  Valid only for the kernel sources they were taken on;
 # any change to those files turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h")
-TRAFFIC = {"sha256": "15c352fa28d78f6f411dbb72c3dbb9939cda2322c19edab09933e5a6f213f6f8",
-           ("split", "fp32", 128, 0): (61.76e6, 70.32e6),
-           ("split", "fp32", 128, 1): (246.48e6, 63.51e6),
-           ("split", "fp64", 128, 0): (124.85e6, 139.53e6),
-           ("split", "fp64", 128, 1): (515.58e6, 124.11e6)}
+TRAFFIC = {"sha256": "eea839342bd0aa5b98c51ff3156ae12ee540de66037bbc0fd1d4f908c32e4fc7",
+           ("split", "fp32", 128, 0): (61.77e6, 70.32e6),
+           ("split", "fp32", 128, 1): (246.13e6, 62.54e6),
+           ("split", "fp64", 128, 0): (124.81e6, 139.47e6),
+           ("split", "fp64", 128, 1): (515.54e6, 124.14e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
