@@ -152,10 +152,10 @@ struct RouteLds {
 #define MFC_XY_WAVES32 5
 #endif
 // the routed variant's LDS (network, feature exchange) admits two workgroups per CU
-// non-uniform cells keep the coefficient rows of the cell in registers: two
-// wavefronts per SIMD
+// non-uniform cells read the tile's coefficient rows from LDS: the FP64
+// kernel then fits two workgroups per CU, the FP32 one four
 template <class T, bool ROUTE, bool STRETCH = false>
-constexpr int kXYWaves = ROUTE || STRETCH ? 2 : (sizeof(T) == 8 ? 3 : MFC_XY_WAVES32);
+constexpr int kXYWaves = ROUTE ? 2 : (STRETCH ? (sizeof(T) == 8 ? 2 : 4) : (sizeof(T) == 8 ? 3 : MFC_XY_WAVES32));
 
 template <class T, bool ROUTE, int ORDER, bool STRETCH, bool KEEP>
 __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
@@ -221,6 +221,24 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
         }
     };
     fetch(z0);
+    // non-uniform cells: the WENO5 coefficient rows of the tile's x cells
+    // (-1 .. TX) and y cells (-1 .. TY), in the arithmetic's type, in LDS
+    // for every plane (in registers they spill or cost occupancy); visible
+    // after the first barrier below
+    constexpr bool kLdsCoef = STRETCH && ORDER == 5;
+    __shared__ T s_cx[kLdsCoef ? (TX + 2) * kStretchCoef : 1];
+    __shared__ T s_cy[kLdsCoef ? (TY + 2) * kStretchCoef : 1];
+    if constexpr (kLdsCoef) {
+        const bool ux = g.wcoef[0] != nullptr, uy = g.wcoef[1] != nullptr;
+        for (int i = tid; i < (TX + 2) * kStretchCoef; i += NT) {
+            const int c = i / kStretchCoef, j = i % kStretchCoef;
+            s_cx[i] = ux ? T(coef_row(g, 0, x0 - 1 + c)[j]) : T(0);
+        }
+        for (int i = tid; i < (TY + 2) * kStretchCoef; i += NT) {
+            const int r = i / kStretchCoef, j = i % kStretchCoef;
+            s_cy[i] = uy ? T(coef_row(g, 1, y0 - 1 + r)[j]) : T(0);
+        }
+    }
 
     for (int k = z0; k < z1; k++) {
         // ---- plane k (own cell + x/y halos) into LDS as primitives
@@ -271,13 +289,12 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
                                                  logit_tau, lane);
             }
             if (valid) {
-                CoefRegs<T> cf;   // one row per cell for all seven variables
-                if constexpr (STRETCH && ORDER == 5) load_coefs<T>(coef_row(g, 0, x0 + c - 1), cf);
+                const T *cl = kLdsCoef && g.wcoef[0] ? &s_cx[c * kStretchCoef] : nullptr;
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     const T *st = &s_plane[v][row + NG][c];
                     if (ROUTE && lin) linear5_pair<T>(st[0], st[1], st[2], st[3], st[4], wP[v], s_minus[v][p]);
-                    else if (STRETCH && ORDER == 5) recon_cell<ORDER, T>(cf, st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
+                    else if (kLdsCoef && cl) weno5_nonuniform_pair<T>(cl, st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
                     else recon_pair<ORDER, T>(st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
                 }
             }
@@ -326,16 +343,15 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
                                                  lane);
             }
             if (valid) {
-                CoefRegs<T> cf;
-                if constexpr (STRETCH && ORDER == 5) load_coefs<T>(coef_row(g, 1, y0 + r - 1), cf);
+                const T *cl = kLdsCoef && g.wcoef[1] ? &s_cy[r * kStretchCoef] : nullptr;
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     if (ROUTE && lin)
                         linear5_pair<T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
                                         s_plane[v][r + 3][li], s_plane[v][r + 4][li], wP[v], s_minus[v][p]);
-                    else if (STRETCH && ORDER == 5)
-                        recon_cell<ORDER, T>(cf, s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
-                                             s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, wP[v], s_minus[v][p]);
+                    else if (kLdsCoef && cl)
+                        weno5_nonuniform_pair<T>(cl, s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
+                                                 s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, wP[v], s_minus[v][p]);
                     else
                         recon_pair<ORDER, T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
                                    s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, wP[v], s_minus[v][p]);
