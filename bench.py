@@ -63,11 +63,11 @@ KERNEL_TIMING_STRIDE = 10
 # WRITE_SIZE x 1.00).  Valid only for the kernel sources they were taken on;
 # any change to those files turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h")
-TRAFFIC = {"sha256": "eea839342bd0aa5b98c51ff3156ae12ee540de66037bbc0fd1d4f908c32e4fc7",
-           ("split", "fp32", 128, 0): (61.77e6, 70.32e6),
-           ("split", "fp32", 128, 1): (246.13e6, 62.54e6),
-           ("split", "fp64", 128, 0): (124.81e6, 139.47e6),
-           ("split", "fp64", 128, 1): (515.54e6, 124.14e6)}
+TRAFFIC = {"sha256": "1ac26a4a42dcee10382dbf918403f58b981e7baef2f2068a3ba3e6175b9fc1dc",
+           ("split", "fp32", 128, 0): (61.76e6, 70.32e6),
+           ("split", "fp32", 128, 1): (246.29e6, 62.41e6),
+           ("split", "fp64", 128, 0): (124.82e6, 139.49e6),
+           ("split", "fp64", 128, 1): (515.55e6, 124.15e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
