@@ -3,9 +3,10 @@
 // Thompson): a post-pass over the boundary cells of every face marked
 // MFC_BC_CHARACTERISTIC, run after the stage kernel of any path.
 //
-// For each boundary cell it recomputes the finite-volume terms normal to
-// the face (the two HLLC fluxes of the cell along that dimension, its share
-// of alpha1 div(u)) and replaces them by the characteristic form: wave
+// For each boundary cell it takes the finite-volume terms normal to the face
+// (the two HLLC fluxes of the cell along that dimension, its share of
+// alpha1 div(u)): kept by the split stage kernels, recomputed here for the
+// fused and staged paths.  It replaces them by the characteristic form: wave
 // amplitudes L1 = (u-c)(p_x - rho c u_x), L5 = (u+c)(p_x + rho c u_x),
 // L_k = u((alpha_k rho_k)_x - alpha_k rho_k p_x/(rho c^2)), L_t = u (u_t)_x,
 // L_a = u (alpha1)_x from second-order one-sided differences into the
