@@ -310,3 +310,25 @@ def test_rk3_equals_composed_primitives():
     qi = oracle.prim_to_cons_field(spec, w)
     err = rel_linf(host(q), host(qs), spec, floor_mom=acoustic_floor(spec, qi))
     assert err.max() <= 1e-14, err
+
+
+def test_kernel_timing_covers_the_enabled_steps_only():
+    """Kernel timing switched on for some steps only: mfc_kernel_time reports
+    the launches of exactly those steps (disabling keeps what was recorded)
+    and resets; the timed durations are positive."""
+    spec, w = W.bubble_collapse_3d(n=32)
+    s = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_SPLIT)
+    q = s.state_from_prim(w)
+    for i in range(5):
+        on = i in (0, 3)
+        if on:
+            mfc.mfc_set_kernel_timing(s.h, True)
+        s.step(q, cfl=0.3)
+        if on:
+            mfc.mfc_set_kernel_timing(s.h, False)
+    ms0, n0 = mfc.mfc_kernel_time(s.h, 0)
+    ms1, n1 = mfc.mfc_kernel_time(s.h, 1)
+    assert n0 == 6 and n1 == 6          # three stages in each of the two timed steps
+    assert ms0 > 0.0 and ms1 > 0.0
+    assert mfc.mfc_kernel_time(s.h, 0) == (0.0, 0)
+    s.check()
