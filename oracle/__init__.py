@@ -23,9 +23,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mfc_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
+_LIB_FMA_PATH = os.path.join(_HERE, "liboracle_fma.so")
 _lib = None
 _lib_omp = None
+_lib_fma = None
 _threaded = False
+_contracted = False
 
 OK = 0
 E_NONPHYSICAL = -4
@@ -34,11 +37,16 @@ E_NONPHYSICAL = -4
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math, no FMA contraction), once
     plain and once with OpenMP (the same source: its pragmas spread the
-    pencils of a sweep over threads; results are bitwise the same)."""
-    for path, extra in ((_LIB_PATH, []), (_LIB_OMP_PATH, ["-fopenmp"])):
+    pencils of a sweep over threads; results are bitwise the same).  A third
+    build of the same source lets the compiler contract a*b + c into fused
+    multiply-adds: another valid rounding order of the same arithmetic, which
+    the parity tests use to measure how far rounding alone moves a result."""
+    builds = ((_LIB_PATH, ["-ffp-contract=off"]), (_LIB_OMP_PATH, ["-ffp-contract=off", "-fopenmp"]),
+              (_LIB_FMA_PATH, ["-ffp-contract=fast", "-mfma"]))
+    for path, extra in builds:
         if force or not os.path.exists(path):
             tmp = path + ".tmp"
-            subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
+            subprocess.run(["gcc", "-O2", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
                             *extra, "-o", tmp, _SRC, "-lm"], check=True)
             os.replace(tmp, path)
     return _LIB_PATH
@@ -68,8 +76,27 @@ def threaded():
         _threaded = prev
 
 
+@contextlib.contextmanager
+def contracted():
+    """Run the oracle calls inside the block on the build with fused
+    multiply-add contraction (single-threaded)."""
+    global _contracted
+    prev = _contracted
+    _contracted = True
+    try:
+        yield
+    finally:
+        _contracted = prev
+
+
 def lib():
-    global _lib, _lib_omp
+    global _lib, _lib_omp, _lib_fma
+    if _contracted:
+        if _lib_fma is None:
+            if not os.path.exists(_LIB_FMA_PATH) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB_FMA_PATH):
+                build(force=True)
+            _lib_fma = _load(_LIB_FMA_PATH)
+        return _lib_fma
     if _threaded:
         if _lib_omp is None:
             if not os.path.exists(_LIB_OMP_PATH) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB_OMP_PATH):

@@ -289,6 +289,14 @@ class Solver:
         mfc_prim_to_cons(self.h, w, q)
         return q
 
+    def upload(self, q_host):
+        """Device copy of a host conservative state of this grid's padded
+        layout, in the storage type (no conversion beyond that rounding)."""
+        import torch
+        if tuple(q_host.shape) != self.shape:
+            raise ValueError(f"state shape {tuple(q_host.shape)} is not the grid's {self.shape}")
+        return torch.as_tensor(q_host, dtype=self.dtype).to("cuda").contiguous()
+
     def fill_ghosts(self, q):
         mfc_fill_ghosts(self.h, q)
 
@@ -523,6 +531,16 @@ class Batch:
         for spec, w in zip(self.specs, ws):
             s = Solver(spec, precision=self.precision)
             qs.append(s.state_from_prim(w))
+            s.close()
+        return qs
+
+    def upload(self, qs_host):
+        """Device copies of host conservative states, one per run, each in
+        its run's padded layout and the storage type."""
+        qs = []
+        for spec, qh in zip(self.specs, qs_host):
+            s = Solver(spec, precision=self.precision)
+            qs.append(s.upload(qh))
             s.close()
         return qs
 

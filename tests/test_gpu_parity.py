@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity_util import acoustic_floor, rel_l1, rel_linf, rhs_err
+from parity_util import rel_l1, rel_linf, rhs_err, rounding_spread, step_bar
 from paper_2305_09163_amd import mfc
 from paper_2305_09163_amd import workloads as W
 
@@ -62,7 +62,10 @@ def needs_3d(kernel, spec):
 
 
 def gpu_state(solver, w):
-    return solver.state_from_prim(w)
+    """The oracle's conservative initial state, uploaded bit for bit: both
+    sides start from identical inputs (the GPU's own primitive ->
+    conservative conversion is checked separately, to 1e-14)."""
+    return solver.upload(oracle.prim_to_cons_field(solver.spec, w))
 
 
 def host(t):
@@ -110,6 +113,7 @@ def test_rhs_parity(name, kernel):
     assert st == oracle.OK
     err = rhs_err(r, ro, qo, spec)
     say(f"    CFL-step error per variable {err}")
+    say(f"    rel Linf of the right-hand side, own scales {rel_linf(r, ro, spec)}")
     assert err.max() <= 1e-12, err
 
 
@@ -128,10 +132,10 @@ def test_one_step_parity(name, kernel):
     qo, to, st = oracle.run(spec, qi, 1, cfl=0.3)
     assert st == oracle.OK
     assert dt == pytest.approx(to, rel=1e-13)
-    say(f"    rel Linf, own scales {rel_linf(host(q), qo, spec)}")
-    err = rel_linf(host(q), qo, spec, floor_mom=acoustic_floor(spec, qi))
-    say(f"    rel Linf per variable {err}")
-    assert err.max() <= 1e-12, err
+    err = rel_linf(host(q), qo, spec)
+    bar = step_bar(rounding_spread(spec, qi, 1, cfl=0.3))
+    say(f"    rel Linf per variable (own scales) {err}; bar {bar}")
+    assert (err <= bar).all(), (err, bar)
 
 
 @pytest.mark.parametrize("kernel", sorted(KERNELS))
@@ -185,8 +189,8 @@ def test_bubble_3d_200_steps_parity():
     qo, to, st = oracle.run(spec, oracle.prim_to_cons_field(spec, w), 200, cfl=0.3)
     assert st == oracle.OK
     assert t == pytest.approx(to, rel=1e-11)
-    err = rel_l1(host(q), qo, spec, floor_mom=acoustic_floor(spec, oracle.prim_to_cons_field(spec, w)))
-    say(f"    rel L1 per variable {err}")
+    err = rel_l1(host(q), qo, spec)
+    say(f"    rel L1 per variable (own scales) {err}")
     assert err.max() <= 1e-10, err
 
 
@@ -203,9 +207,10 @@ def test_full_size_bubble_one_step_parity():
     qi = oracle.prim_to_cons_field(spec, w)
     qo, _, st = oracle.run(spec, qi, 1, cfl=0.3)
     assert st == oracle.OK
-    err = rel_linf(host(q), qo, spec, floor_mom=acoustic_floor(spec, qi))
-    say(f"    rel Linf per variable {err}")
-    assert err.max() <= 1e-12, err
+    err = rel_linf(host(q), qo, spec)
+    bar = step_bar(rounding_spread(spec, qi, 1, cfl=0.3))
+    say(f"    rel Linf per variable (own scales) {err}; bar {bar}")
+    assert (err <= bar).all(), (err, bar)
 
 
 def test_max_wavespeed_parity():
@@ -236,6 +241,7 @@ def test_full_size_bubble_rhs_parity(kernel):
     assert st == oracle.OK
     err = rhs_err(r, ro, qo, spec)
     say(f"    CFL-step error per variable {err}")
+    say(f"    rel Linf of the right-hand side, own scales {rel_linf(r, ro, spec)}")
     assert err.max() <= 1e-12, err
 
 
@@ -307,8 +313,7 @@ def test_rk3_equals_composed_primitives():
         s.fill_ghosts(qs)
         L = s.rhs(qs)
         qs = a * q0 + b * (qs + dt * L)
-    qi = oracle.prim_to_cons_field(spec, w)
-    err = rel_linf(host(q), host(qs), spec, floor_mom=acoustic_floor(spec, qi))
+    err = rel_linf(host(q), host(qs), spec)
     assert err.max() <= 1e-14, err
 
 

@@ -79,3 +79,34 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"no pin failed for mutant '{name}':\n{r.stdout[-2000:]}"
+
+# Planted mistakes in the indicator oracle (Python source; a mutated copy is
+# loaded as a module and the pins that take the module as an argument run on
+# it).
+IND_SRC = os.path.join(ROOT, "oracle", "indicator.py")
+IND_MUTANTS = {
+    "adam without bias correction": ("mhat = m / (1.0 - b1 ** t)\n        vhat = v / (1.0 - b2 ** t)",
+                                     "mhat = m\n        vhat = v"),
+    "adam |g| in the second moment": ("(1.0 - b2) * grads[k] ** 2", "(1.0 - b2) * np.abs(grads[k])"),
+    "adam eps inside the square root": ("(np.sqrt(vhat) + eps)", "np.sqrt(vhat + eps)"),
+    "adam first moment decay": ("m[...] = b1 * m + (1.0 - b1) * grads[k]", "m[...] = b2 * m + (1.0 - b2) * grads[k]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(IND_MUTANTS))
+def test_indicator_pins_catch_planted_mistake(name):
+    import importlib.util
+    import test_oracle_adam as pins
+    old, new = IND_MUTANTS[name]
+    src = open(IND_SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not found exactly once: {old!r}"
+    spec = importlib.util.spec_from_loader("indicator_mutant", loader=None)
+    mod = importlib.util.module_from_spec(spec)
+    exec(compile(src.replace(old, new), "indicator_mutant.py", "exec"), mod.__dict__)
+    caught = 0
+    for check in (pins.check_first_step_closed_form, pins.check_matches_torch):
+        try:
+            check(mod)
+        except AssertionError:
+            caught += 1
+    assert caught > 0, f"no Adam pin failed for mutant '{name}'"
