@@ -129,7 +129,10 @@ typedef struct {
 } mfc_grid_desc;
 
 /* Create a grid handle from *desc (validated; see mfc_grid_desc) and
- * allocate its device scratch on the current HIP device.
+ * allocate its device scratch on the current HIP device.  The grid is the
+ * Cartesian finite-volume mesh of Sec. 3.1 (cell averages on uniform cells,
+ * or on the non-uniform cells of Sec. 4.1), with the two stiffened-gas
+ * fluids of Sec. 2.1 (eq. soe) and the boundary buffers of Sec. 3.3.
  * Returns MFC_E_ARG, MFC_E_UNSUPPORTED or MFC_E_NOMEM on failure, with *out
  * set to NULL. */
 int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out);
@@ -167,14 +170,19 @@ int mfc_fill_ghosts(mfc_grid *g, void *q, void *stream);
  * whatever the ghost cells of q hold. */
 int mfc_rhs(mfc_grid *g, const void *q, void *rhs, void *stream);
 
-/* Largest signal speed max_cells max_d (|u_d| + c) over interior cells
+/* Largest signal speed max_cells max_d (|u_d| + c) over interior cells, the
+ * quantity that bounds the explicit step through the CFL condition (Sec. 1;
+ * c the frozen mixture sound speed of the stiffened-gas mixture, Sec. 2.1)
  * (ghosts not read); on a grid with non-uniform cells the largest
  * (|u_d| + c)/dx_d(cell) instead (1/s).  Synchronises the stream and writes
  * *smax_host.  Returns MFC_E_NONPHYSICAL if an interior cell is
  * non-physical. */
 int mfc_max_wavespeed(mfc_grid *g, const void *q, double *smax_host, void *stream);
 
-/* One third-order TVD (SSP) Runge-Kutta step in place on q, ghost fill
+/* One third-order TVD (SSP) Runge-Kutta step in place on q (Sec. 3.4:
+ * q1 = q + dt L(q), q2 = 3/4 q + 1/4 (q1 + dt L(q1)),
+ * q^{n+1} = 1/3 q + 2/3 (q2 + dt L(q2)), L the right-hand side of eq.
+ * (fvmdis) as in mfc_rhs), ghost fill
  * before every right-hand side (MFC_KERNEL_SPLIT applies the boundary
  * conditions by index instead, with the same result, and leaves the ghost
  * cells of q as they were).  If cfl > 0 the step size is
