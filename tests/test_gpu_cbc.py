@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import oracle
-from parity_util import acoustic_floor, rel_l1, rel_linf, rhs_err, rounding_spread, step_bar
+from parity_util import acoustic_floor, rel_l1, rel_linf, rhs_err, rounding_spread, run_parity, step_bar
 from paper_2305_09163_amd import mfc
 from paper_2305_09163_amd import workloads as W
 
@@ -161,7 +161,7 @@ def test_cbc_200_steps_3d(kernel):
     assert abs(s.time()[0] - t) <= 1e-12 * t
     e = rel_l1(q.cpu().numpy(), qn, spec)
     say(f"    200-step rel L1 {e.max():.2e}")
-    assert e.max() <= 1e-10
+    run_parity(e, spec, q0, 200, cfl=0.3)
 
 
 def pulse(n=200):
@@ -197,7 +197,7 @@ def test_pulse_leaves_without_reflection(kernel):
     e = rel_l1(q.cpu().numpy(), qn, spec)
     say(f"    residual {resid / (1e-3 * p0):.2e} of the amplitude, rel L1 vs oracle {e.max():.2e}")
     assert resid < 1e-4 * 1e-3 * p0
-    assert e.max() <= 1e-10
+    run_parity(e, spec, q0, 1100, cfl=0.4)
 
 
 def test_cbc_fp32_error():
