@@ -88,18 +88,25 @@ def measured_traffic(kernel, precision, recon, model, stretch, n, slot, bc="extr
     return TRAFFIC.get((kernel, precision, n, slot))
 
 
-def error_vs_reference(spec, w, make_solver, steps, mfc, weights, tau):
-    """Relative L1 density error of this form against the FP64 WENO5 path
-    (the path the parity tests check against the oracle) after `steps`
-    steps of one fixed dt (CFL 0.3 of the initial state) from the same
-    initial state; with a network, also the share of interior (cell,
-    direction) reconstructions it routes to the linear stencil at the end."""
+def reference_run(spec, w, steps, mfc):
+    """The FP64 WENO5 path (the one the parity tests check against the
+    oracle) advanced `steps` steps of one fixed dt, CFL 0.3 of the initial
+    state; the forms are compared with it after the same steps."""
     ref = mfc.Solver(spec, kernel=mfc.MFC_KERNEL_SPLIT if spec.faces is None else mfc.MFC_KERNEL_FUSED,
                      precision=mfc.MFC_FP64)
     qr = ref.state_from_prim(w)
     dt = 0.3 * min(spec.dx[:spec.ndim]) / ref.max_wavespeed(qr)
     ref.run(qr, steps, dt=dt)
     ref.check()
+    return ref, qr, dt
+
+
+def error_vs_reference(spec, w, make_solver, steps, mfc, weights, tau, reference=None):
+    """Relative L1 density error of this form against the FP64 WENO5 path
+    after `steps` steps of one fixed dt from the same initial state; with a
+    network, also the share of interior (cell, direction) reconstructions it
+    routes to the linear stencil at the end."""
+    ref, qr, dt = reference or reference_run(spec, w, steps, mfc)
     s = make_solver()
     q = s.state_from_prim(w)
     s.run(q, steps, dt=dt)
@@ -118,11 +125,55 @@ def error_vs_reference(spec, w, make_solver, steps, mfc, weights, tau):
     return out
 
 
-def cpu_baseline(spec, w):
+def timed_run(torch, mfc, solver, q, steps, warmup, cfl):
+    """Advance q by `warmup` untimed and `steps` timed SSP-RK3 steps; the
+    library's kernel events cover every KERNEL_TIMING_STRIDE-th timed step.
+    Returns the elapsed seconds and (ms, launches) of both kernel slots."""
+    for _ in range(warmup):
+        solver.step(q, cfl=cfl)
+    torch.cuda.synchronize()
+    solver.check()
+    mfc.mfc_kernel_time(solver.h, 0)   # nothing recorded before the timed region
+    mfc.mfc_kernel_time(solver.h, 1)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(steps):
+        # the library's per-launch HIP events bracket the kernels of every
+        # KERNEL_TIMING_STRIDE-th step: events between all launches would
+        # lengthen every step by about 4 %
+        sample = i % KERNEL_TIMING_STRIDE == 0
+        if sample:
+            mfc.mfc_set_kernel_timing(solver.h, True)
+        solver.step(q, cfl=cfl)
+        if sample:
+            mfc.mfc_set_kernel_timing(solver.h, False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k0 = mfc.mfc_kernel_time(solver.h, 0)
+    k1 = mfc.mfc_kernel_time(solver.h, 1)
+    solver.check()
+    return max(wall, e0.elapsed_time(e1) / 1e3), k0, k1
+
+
+def cpu_baseline(spec, w, workload="bubble"):
     """The FP64 oracle on the host for one SSP-RK3 step of the same workload:
     the plain single-threaded build, and the OpenMP build of the same source
-    on every host core it is given (OMP_NUM_THREADS, else all cores)."""
+    on every host core it is given (OMP_NUM_THREADS, else all cores).  Above
+    128^3 cells the sample is the same workload generated at 128^3 (one step
+    of 256^3 takes the single-threaded oracle about 40 s)."""
     import oracle
+    from paper_2305_09163_amd import workloads as W
+
+    name = "bubble cloud" if workload == "cloud" else "bubble"
+    if spec.cells > 128 ** 3 and spec.faces is None:
+        import dataclasses
+        gen = W.bubble_cloud_3d if workload == "cloud" else W.bubble_collapse_3d
+        s2, w = gen(n=128)
+        spec = dataclasses.replace(s2, model=spec.model, bc=spec.bc)
 
     def one_step():
         q = oracle.prim_to_cons_field(spec, w)
@@ -135,7 +186,7 @@ def cpu_baseline(spec, w):
     el = one_step()
     with oracle.threaded() as threads:
         el_t = one_step()
-    sample = f"1 SSP-RK3 step (3 RHS evaluations) of the {spec.n[0]}^3 bubble workload"
+    sample = f"1 SSP-RK3 step (3 RHS evaluations) of the {spec.n[0]}^3 {name} workload"
     return {"value": spec.cells * 3 / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{sample}, single-threaded C oracle (gcc -O2), {el:.1f} s",
             "host_cpus": os.cpu_count(),
@@ -225,8 +276,13 @@ def main():
     ap.add_argument("--kernel", choices=["fused", "staged", "split"], default="split")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["bubble", "ensemble"], default="bubble",
-                    help="bubble: the 3D bubble collapse (default); ensemble: 64 uneven 2D droplet-shock runs")
+    ap.add_argument("--workload", choices=["bubble", "cloud", "ensemble"], default="bubble",
+                    help="bubble: the 3D bubble collapse (default); cloud: 50 bubbles struck by a pressure "
+                         "step (3D, use --n 256 --precision fp32 --steps 50); ensemble: 64 uneven 2D "
+                         "droplet-shock runs")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="time only the requested form (the default FP64 line also times the FP32 and "
+                         "learned forms)")
     ap.add_argument("--recon", choices=["weno5", "learned", "weno3", "first"], default="weno5",
                     help="learned: reconstruction routed by the trained indicator (weights from --weights); "
                          "weno3 / first: the third- and first-order reconstructions")
@@ -260,16 +316,26 @@ def main():
         return bench_ensemble(args, torch, mfc, W)
     if args.stretch > 0.0 and args.kernel == "staged":
         sys.exit("bench.py: stretched grids run on the split or the fused kernel")
-    spec, w = W.bubble_collapse_3d(n=args.n, stretch=args.stretch)
+    if args.workload == "cloud":
+        spec, w = W.bubble_cloud_3d(n=args.n)
+    else:
+        spec, w = W.bubble_collapse_3d(n=args.n, stretch=args.stretch)
     if args.model == "kapila":
         import dataclasses
         spec = dataclasses.replace(spec, model=1)
     if args.bc == "characteristic":
         import dataclasses
         spec = dataclasses.replace(spec, bc=(mfc.MFC_BC_CHARACTERISTIC,) * 6)
-    kernel = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}[args.kernel]
-    precision = mfc.MFC_FP64 if args.precision == "fp64" else mfc.MFC_FP32_MIXED
-    learned = args.recon == "learned"
+    kernels = {"fused": mfc.MFC_KERNEL_FUSED, "staged": mfc.MFC_KERNEL_STAGED, "split": mfc.MFC_KERNEL_SPLIT}
+    precisions = {"fp64": mfc.MFC_FP64, "fp32": mfc.MFC_FP32_MIXED}
+    recons = {"weno5": mfc.MFC_RECON_WENO5, "learned": mfc.MFC_RECON_LEARNED, "weno3": mfc.MFC_RECON_WENO3,
+              "first": mfc.MFC_RECON_FIRST_ORDER}
+    # the default line (FP64 WENO5 on the split kernels) also times the FP32
+    # and learned forms on the same workload: the metric compares them
+    default_form = (args.kernel == "split" and args.precision == "fp64" and args.recon == "weno5"
+                    and args.model == "allaire" and args.stretch == 0.0 and args.bc == "extrap")
+    compare = default_form and not args.no_forms
+    learned = args.recon == "learned" or compare
     weights = None
     if learned:
         import numpy as np
@@ -281,56 +347,28 @@ def main():
             meta = os.path.splitext(args.weights)[0] + ".json"
             args.tau = json.load(open(meta))["tau"] if os.path.exists(meta) else 0.5
 
-    recon = {"weno5": mfc.MFC_RECON_WENO5, "learned": mfc.MFC_RECON_LEARNED, "weno3": mfc.MFC_RECON_WENO3,
-             "first": mfc.MFC_RECON_FIRST_ORDER}[args.recon]
+    def solver_factory(precision, recon):
+        def make():
+            s = mfc.Solver(spec, kernel=kernels[args.kernel], precision=precisions[precision],
+                           recon=recons[recon])
+            if recon == "learned":
+                s.set_indicator(weights, args.tau)
+            return s
+        return make
 
-    def make_solver():
-        s = mfc.Solver(spec, kernel=kernel, precision=precision, recon=recon)
-        if learned:
-            s.set_indicator(weights, args.tau)
-        return s
-
+    make_solver = solver_factory(args.precision, args.recon)
     solver = make_solver()
     q = solver.state_from_prim(w)
     cfl = 0.3
-    for _ in range(args.warmup):
-        solver.step(q, cfl=cfl)
-    torch.cuda.synchronize()
-    solver.check()
-
-    mfc.mfc_kernel_time(solver.h, 0)   # nothing recorded before the timed region
-    mfc.mfc_kernel_time(solver.h, 1)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for i in range(args.steps):
-        # the library's per-launch HIP events bracket the kernels of every
-        # KERNEL_TIMING_STRIDE-th step: events between all launches would
-        # lengthen every step by about 4 %
-        sample = i % KERNEL_TIMING_STRIDE == 0
-        if sample:
-            mfc.mfc_set_kernel_timing(solver.h, True)
-        solver.step(q, cfl=cfl)
-        if sample:
-            mfc.mfc_set_kernel_timing(solver.h, False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_kernel, launches = mfc.mfc_kernel_time(solver.h, 0)
-    ms_kernel1, launches1 = mfc.mfc_kernel_time(solver.h, 1)
-    solver.check()
-    ev_s = e0.elapsed_time(e1) / 1e3
-    elapsed = max(wall, ev_s)
-
+    elapsed, (ms_kernel, launches), (ms_kernel1, launches1) = timed_run(torch, mfc, solver, q, args.steps,
+                                                                        args.warmup, cfl)
     updates = spec.cells * 3 * args.steps
     value = updates / elapsed
-    # the FP32 form's arithmetic is FP32 except the pressure recovery and s*
-    peak_alu = PEAK_FP64_VALU if args.precision == "fp64" else PEAK_FP32_VALU
 
-    def roofline(ms, n, name, flops, nbytes, slot=0):
-        nbytes = nbytes * (1.0 if args.precision == "fp64" else 0.5)  # byte counts above are for 8-byte values
+    def roofline(ms, n, name, flops, nbytes, precision, slot=0):
+        # the FP32 form's arithmetic is FP32 except the pressure recovery and s*
+        peak_alu = PEAK_FP64_VALU if precision == "fp64" else PEAK_FP32_VALU
+        nbytes = nbytes * (1.0 if precision == "fp64" else 0.5)  # byte counts above are for 8-byte values
         avg = ms / 1e3 / max(n, 1)
         achieved = flops * spec.cells / avg
         hbm = nbytes * spec.cells / avg
@@ -339,8 +377,8 @@ def main():
              "frac": achieved / peak_alu, "traffic": None}
         if bound == "hbm":
             r.update(achieved=hbm / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=hbm / PEAK_HBM)
-        tr = measured_traffic(args.kernel, args.precision, args.recon, args.model, args.stretch, args.n, slot,
-                              args.bc)
+        tr = measured_traffic(args.kernel, precision, args.recon, args.model, args.stretch, args.n, slot,
+                              args.bc) if args.workload == "bubble" else None
         if tr:
             # measured HBM bytes per launch over the same average launch duration
             r.update(traffic=sum(tr) / avg / 1e9, traffic_unit="GB/s",
@@ -353,30 +391,60 @@ def main():
         return r
 
     if args.kernel == "split":
-        roof = roofline(ms_kernel, launches, SPLIT[0]["name"], SPLIT[0]["flops"], SPLIT[0]["bytes"])
-        roof_z = roofline(ms_kernel1, launches1, SPLIT[1]["name"], SPLIT[1]["flops"], SPLIT[1]["bytes"], slot=1)
+        roof = roofline(ms_kernel, launches, SPLIT[0]["name"], SPLIT[0]["flops"], SPLIT[0]["bytes"], args.precision)
+        roof_z = roofline(ms_kernel1, launches1, SPLIT[1]["name"], SPLIT[1]["flops"], SPLIT[1]["bytes"],
+                          args.precision, slot=1)
     else:
         name = "k_fused<3> (fused RHS + stage update)" if args.kernel == "fused" else "staged RHS sequence"
-        roof = roofline(ms_kernel, launches, name, FLOPS_PER_CELL_UPDATE, BYTES_PER_CELL_UPDATE)
+        roof = roofline(ms_kernel, launches, name, FLOPS_PER_CELL_UPDATE, BYTES_PER_CELL_UPDATE, args.precision)
         roof_z = None
     t, _ = solver.time()
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
            "data": "synthetic",
-           "config": {"workload": f"bubble_collapse_3d_{args.n}", "cells": spec.cells, "nvar": spec.nvar,
+           "config": {"workload": f"{'bubble_cloud' if args.workload == 'cloud' else 'bubble_collapse'}_3d_{args.n}",
+                      "cells": spec.cells, "nvar": spec.nvar,
                       "cfl": cfl, "precision": args.precision, "kernel": args.kernel, "recon": args.recon,
                       "model": args.model, "stretch": args.stretch, "bc": args.bc,
                       "parallelism": "single GPU"},
            "roofline": roof, "simulated_time_s": t, "cell_steps_per_s": value / 3}
-    if learned:
+    if args.recon == "learned":
         out["config"]["tau"] = args.tau
     if roof_z:
         out["roofline_second_kernel"] = roof_z
+    reference = None
+    if args.precision == "fp32" or args.recon != "weno5" or compare:
+        reference = reference_run(spec, w, args.steps, mfc)
     if args.precision == "fp32" or args.recon != "weno5":
-        out["error_vs_fp64_weno5"] = error_vs_reference(spec, w, make_solver, args.steps, mfc, weights, args.tau)
+        out["error_vs_fp64_weno5"] = error_vs_reference(spec, w, make_solver, args.steps, mfc,
+                                                        weights if args.recon == "learned" else None, args.tau,
+                                                        reference)
+    if compare:
+        # the metric's comparison: each form timed on the same workload and
+        # steps, its rate against this line's FP64 rate, and its relative L1
+        # density error against the FP64 path after the same steps
+        forms = {}
+        for precision, recon in (("fp32", "weno5"), ("fp64", "learned"), ("fp32", "learned")):
+            mk = solver_factory(precision, recon)
+            s2 = mk()
+            q2 = s2.state_from_prim(w)
+            el2, (msa, na), (msb, nb) = timed_run(torch, mfc, s2, q2, args.steps, args.warmup, cfl)
+            v2 = updates / el2
+            f = {"value": v2, "unit": "cell-updates/s", "ms_per_step": el2 / args.steps * 1e3,
+                 "ratio_to_fp64": v2 / value, "precision": precision, "recon": recon,
+                 "kernel_avg_launch_us": {"k_xy": msa / max(na, 1) * 1e3, "k_z": msb / max(nb, 1) * 1e3}}
+            if recon == "learned":
+                f["tau"] = args.tau
+            f.update(error_vs_reference(spec, w, mk, args.steps, mfc, weights if recon == "learned" else None,
+                                        args.tau, reference))
+            f["meets_target"] = bool(f["ratio_to_fp64"] >= 1.8 and f["rel_l1_density"] <= 1e-4)
+            forms[f"{precision}_{recon}"] = f
+            del s2, q2
+        out["forms"] = forms
+        out["forms_target"] = "ratio_to_fp64 >= 1.8 at rel_l1_density <= 1e-4 against the FP64 path"
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, w)
+        out["cpu_baseline"] = cpu_baseline(spec, w, args.workload)
     print(json.dumps(out), flush=True)
     if args.copy_probe:
         copy_probe(torch, args.copy_probe)

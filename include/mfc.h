@@ -188,10 +188,12 @@ int mfc_max_wavespeed(mfc_grid *g, const void *q, double *smax_host, void *strea
  * cells of q as they were).  If cfl > 0 the step size is
  * cfl * min_d dx_d / max_wavespeed(q^n), computed on the device with no host
  * synchronisation; otherwise dt (> 0) is used.  The step size taken and the
- * accumulated time are kept on the device (mfc_time). */
-int mfc_rk3_step(mfc_grid *g, void *q, double cfl, double dt, void *stream);
+ * accumulated time are kept on the device (mfc_time); if dt_used_dev is not
+ * NULL, the step size taken is also written, on the stream and with no host
+ * synchronisation, to that caller-owned device double. */
+int mfc_rk3_step(mfc_grid *g, void *q, double cfl, double dt, double *dt_used_dev, void *stream);
 
-/* nsteps calls of mfc_rk3_step, enqueued back to back. */
+/* nsteps calls of mfc_rk3_step (dt_used_dev NULL), enqueued back to back. */
 int mfc_run(mfc_grid *g, void *q, int nsteps, double cfl, double dt, void *stream);
 
 /* Synchronise and read the accumulated simulated time and the last step

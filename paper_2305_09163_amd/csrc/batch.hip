@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kBT) k_batch_wavespeed(const RunDev<T> *__rest
         bad |= cons_to_prim<2, T>(g, qc, wc);
         double Gam, Pi;
         mixture<double>(g, double(wc[5]), Gam, Pi);
-        const double cs = __builtin_sqrt(sound2<double>(Gam, Pi, double(wc[0]) + double(wc[1]), double(wc[4])));
+        const double cs = sqrtT(sound2<double>(Gam, Pi, double(wc[0]) + double(wc[1]), double(wc[4])));
         smax = __builtin_fmax(smax, __builtin_fmax(__builtin_fabs(double(wc[2])), __builtin_fabs(double(wc[3]))) + cs);
     }
     if (bad) atomicOr(flag, 2);

@@ -18,6 +18,7 @@
 // right-hand side, the difference itself).  Neighbours past a face are read
 // through the boundary rule (the adjacent interior cell), so the ghost
 // cells need not be filled.
+#include "charbc.h"
 #include "internal.h"
 
 namespace mfc {
@@ -118,44 +119,11 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
     fv[A] += W[0][A] * ((half ? uf - uother : uother - uf) * idx);
     }
 
-    // characteristic form on the boundary cell: second-order one-sided
-    // differences into the domain
-    const T *wb = W[0];
-    T dw[NV];
+    // characteristic form on the boundary cell
+    T rate[NV];
+    bad |= char_rate<NDIM, D, SIDE, T>(g, W[0], W[1], W[2], idx, rate);
 #pragma unroll
-    for (int v = 0; v < NV; v++) dw[v] = T(sg) * (T(-3) * wb[v] + T(4) * W[1][v] - W[2][v]) * (T(0.5) * idx);
-    T Gam, Pi;
-    mixture<T>(g, wb[A], Gam, Pi);
-    const T rho = wb[0] + wb[1], p = wb[E], un = wb[2 + D];
-    const T c2 = sound2<T>(Gam, Pi, rho, p), cs = sqrtT(c2);
-    bad |= nonphysical<T>(rho, c2);
-    // a wave enters through the low face when it moves to +x, through the
-    // high face when it moves to -x
-    auto enters = [](T lam) { return SIDE == 0 ? lam > T(0) : lam < T(0); };
-    const T lam1 = un - cs, lam5 = un + cs;
-    const T L1 = enters(lam1) ? T(0) : lam1 * (dw[E] - rho * cs * dw[2 + D]);
-    const T L5 = enters(lam5) ? T(0) : lam5 * (dw[E] + rho * cs * dw[2 + D]);
-    const bool in_m = enters(un);
-    const T irc2 = rcp(rho * c2), S = T(0.5) * (L5 + L1);
-    T rkt[2];
-#pragma unroll
-    for (int k = 0; k < 2; k++) rkt[k] = -(in_m ? T(0) : un * (dw[k] - wb[k] * irc2 * dw[E])) - wb[k] * irc2 * S;
-    T ut[NDIM];
-#pragma unroll
-    for (int m = 0; m < NDIM; m++) ut[m] = m == D ? -(L5 - L1) * rcp(T(2) * rho * cs) : (in_m ? T(0) : -un * dw[2 + m]);
-    const T pt = -S, at_ = in_m ? T(0) : -un * dw[A];
-    const T rhot = rkt[0] + rkt[1];
-    T u2 = T(0), uut = T(0);
-    delta[0] += rkt[0] - fv[0];
-    delta[1] += rkt[1] - fv[1];
-#pragma unroll
-    for (int m = 0; m < NDIM; m++) {
-        delta[2 + m] += (wb[2 + m] * rhot + rho * ut[m]) - fv[2 + m];
-        u2 += wb[2 + m] * wb[2 + m];
-        uut += wb[2 + m] * ut[m];
-    }
-    delta[E] += (Gam * pt + (T(g.g1 - g.g2) * p + T(g.h1 - g.h2)) * at_ + T(0.5) * u2 * rhot + rho * uut) - fv[E];
-    delta[A] += at_ - fv[A];
+    for (int v = 0; v < NV; v++) delta[v] += rate[v] - fv[v];
     return bad;
 }
 
@@ -229,9 +197,13 @@ void launch_t(mfc_grid *h, const void *q, void *out, int mode, double dt, const 
     const Grid &g = h->g;
     CbcFaces F{};
     int64_t total = 0;
+    // the split path (3D) applies the x and y faces inside its x+y kernel
+    // and keeps the normal terms of the z faces' cells; the other paths
+    // recompute them here for every face
+    const bool stored = g.cbc_mask != 0;
     for (int f = 0; f < 6; f++) {
         F.start[f] = total;
-        if (f >= 2 * g.ndim || g.bc[f] != MFC_BC_CHARACTERISTIC) continue;
+        if (f >= 2 * g.ndim || g.bc[f] != MFC_BC_CHARACTERISTIC || (stored && f < 4)) continue;
         const int d = f >> 1;
         F.mask |= 1 << f;
         // inactive dimensions have n = 1
@@ -239,8 +211,6 @@ void launch_t(mfc_grid *h, const void *q, void *out, int mode, double dt, const 
     }
     F.start[6] = total;
     if (F.mask == 0) return;
-    // the split path (3D) keeps the normal terms; the others recompute them
-    const bool stored = g.cbc_mask != 0;
     const int lanes = stored ? 1 : 2;
     const dim3 grid((unsigned)((lanes * total + kCbcThreads - 1) / kCbcThreads));
     const T *a = (const T *)q;

@@ -27,7 +27,7 @@ struct mfc_grid {
     double *recp = nullptr;    // staged path: reconstruction at x_{i+1/2}, per cell
     double *recm = nullptr;    // staged path: reconstruction at x_{i-1/2}, per cell
     double *faces = nullptr;   // staged path: 3 directions x (nvar + 1) face arrays
-    double *lxy = nullptr;     // split path: x+y flux differences and div(u), nvar + 1 arrays
+    double *lxy = nullptr;     // split path: x+y part of each cell's right-hand side or stage result, nvar arrays
     void *cbc_fv = nullptr;    // split path: normal terms of characteristic boundary cells
     double *partial = nullptr; // per-block maxima of the wave-speed reduction
     int64_t partial_len = 0;   // its length (the larger of the two producers' grids)
@@ -48,9 +48,16 @@ constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
 
 // status helpers
+int fail(int status, const char *detail);
 int fail(int status, const std::string &detail);
 // Kapila coefficients of a grid from its descriptor (model, gamma, pi_inf)
 void set_kapila(Grid &g, const mfc_grid_desc &d);
+// The kernels' geometry and material constants of a validated descriptor
+// (host only; no device tables: non-uniform and characteristic-boundary
+// fields are left empty)
+void make_grid(const mfc_grid_desc &d, Grid &g);
+// Checks of mfc_init_grid on a descriptor (MFC_OK or the failure status)
+int validate_desc(const mfc_grid_desc *d);
 // Device tables of a non-uniform grid (stretch.hip): built at init from the
 // descriptor's face coordinates, released with the handle.
 int build_stretch_tables(mfc_grid *h, const mfc_grid_desc *d);

@@ -13,17 +13,21 @@ namespace mfc {
 
 static thread_local char g_detail[512] = "";
 
-int fail(int status, const std::string &detail)
+// The detail of a failure is formatted into a fixed thread-local buffer (no
+// heap allocation on the error paths).
+int fail(int status, const char *detail)
 {
-    std::snprintf(g_detail, sizeof g_detail, "%s", detail.c_str());
+    std::snprintf(g_detail, sizeof g_detail, "%s", detail);
     return status;
 }
+
+int fail(int status, const std::string &detail) { return fail(status, detail.c_str()); }
 
 int hip_status(hipError_t e, const char *what)
 {
     if (e == hipSuccess) return MFC_OK;
-    return fail(e == hipErrorOutOfMemory ? MFC_E_NOMEM : MFC_E_HIP,
-                std::string(what) + ": " + hipGetErrorString(e));
+    std::snprintf(g_detail, sizeof g_detail, "%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? MFC_E_NOMEM : MFC_E_HIP;
 }
 
 void timing_begin(mfc_grid *h, hipStream_t s, int slot)
@@ -54,6 +58,37 @@ void set_kapila(Grid &g, const mfc_grid_desc &d)
         g.zg[k] = d.gamma[k];
         g.zp[k] = d.gamma[k] * d.pi_inf[k];
     }
+}
+
+void make_grid(const mfc_grid_desc &desc, Grid &g)
+{
+    g = Grid{};
+    g.ndim = desc.ndim;
+    for (int d = 0; d < 3; d++) {
+        bool act = d < desc.ndim;
+        g.n[d] = act ? desc.n[d] : 1;
+        g.off[d] = act ? NG : 0;
+        g.p[d] = act ? desc.n[d] + 2 * NG : 1;
+        g.inv_dx[d] = act ? desc.n[d] / (desc.hi[d] - desc.lo[d]) : 0.0;
+        g.bc[2 * d] = act ? desc.bc[2 * d] : MFC_BC_EXTRAP;
+        g.bc[2 * d + 1] = act ? desc.bc[2 * d + 1] : MFC_BC_EXTRAP;
+    }
+    g.dxmin = 1e300;
+    for (int d = 0; d < desc.ndim; d++) g.dxmin = std::fmin(g.dxmin, (desc.hi[d] - desc.lo[d]) / desc.n[d]);
+    g.stride[0] = 1;
+    g.stride[1] = g.p[0];
+    g.stride[2] = (int64_t)g.p[0] * g.p[1];
+    g.vstride = (int64_t)g.p[0] * g.p[1] * g.p[2];
+    g.g1 = 1.0 / (desc.gamma[0] - 1.0);
+    g.g2 = 1.0 / (desc.gamma[1] - 1.0);
+    g.h1 = desc.gamma[0] * desc.pi_inf[0] / (desc.gamma[0] - 1.0);
+    g.h2 = desc.gamma[1] * desc.pi_inf[1] / (desc.gamma[1] - 1.0);
+    g.eps = desc.weno_eps;
+    set_kapila(g, desc);
+    g.order = desc.recon == MFC_RECON_WENO3 ? 3 : (desc.recon == MFC_RECON_FIRST_ORDER ? 1 : 5);
+    g.stretched = 0;
+    for (int d = 0; d < desc.ndim; d++) g.stretched |= desc.faces[d] != nullptr;
+    if (g.stretched) g.dxmin = 1.0;   // the reduction then returns max (|u_d| + c)/dx_d
 }
 
 namespace {
@@ -171,7 +206,7 @@ __global__ void __launch_bounds__(kReduceThreads) k_wavespeed(Grid g, const T *_
         bad |= cons_to_prim<NDIM, T>(g, qc, wc);
         double Gam, Pi;
         mixture<double>(g, double(wc[A]), Gam, Pi);
-        double cs = __builtin_sqrt(sound2<double>(Gam, Pi, double(wc[0]) + double(wc[1]), double(wc[E])));
+        double cs = sqrtT(sound2<double>(Gam, Pi, double(wc[0]) + double(wc[1]), double(wc[E])));
         if (g.stretched) {
             // non-uniform cells: the largest (|u_d| + c)/dx_d (the CFL step is cfl over it)
             const int idx[3] = {i, j, k};
@@ -222,6 +257,13 @@ __global__ void __launch_bounds__(kReduceThreads) k_step_begin(const double *__r
         scalars[1] = dt;
         scalars[2] += dt;
     }
+}
+
+// The step size the last step took (scalars[1]) into the caller's device
+// word (mfc_rk3_step's dt_used_dev).
+__global__ void k_copy_dt(const double *__restrict__ scalars, double *__restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = scalars[1];
 }
 
 __global__ void k_set_scalars(double *scalars, int *flag, int what)
@@ -373,6 +415,9 @@ int64_t elem_bytes(const mfc_grid *h) { return is_fp32(h) ? 4 : 8; }
 int64_t state_bytes(const mfc_grid *h) { return (int64_t)h->nvar * h->cells_padded * elem_bytes(h); }
 
 }  // namespace
+
+int validate_desc(const mfc_grid_desc *d) { return validate(d); }
+
 }  // namespace mfc
 
 using namespace mfc;
@@ -419,36 +464,12 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
     if (!h) return fail(MFC_E_NOMEM, "host allocation failed");
     h->desc = *desc;
     Grid &g = h->g;
-    g.ndim = desc->ndim;
+    make_grid(*desc, g);
     h->nvar = 4 + desc->ndim;
-    for (int d = 0; d < 3; d++) {
-        bool act = d < desc->ndim;
-        g.n[d] = act ? desc->n[d] : 1;
-        g.off[d] = act ? NG : 0;
-        g.p[d] = act ? desc->n[d] + 2 * NG : 1;
-        g.inv_dx[d] = act ? desc->n[d] / (desc->hi[d] - desc->lo[d]) : 0.0;
-        if (!act) {
-            h->desc.n[d] = 1;
-            h->desc.bc[2 * d] = h->desc.bc[2 * d + 1] = MFC_BC_EXTRAP;
-        }
+    for (int d = desc->ndim; d < 3; d++) {
+        h->desc.n[d] = 1;
+        h->desc.bc[2 * d] = h->desc.bc[2 * d + 1] = MFC_BC_EXTRAP;
     }
-    g.dxmin = 1e300;
-    for (int d = 0; d < desc->ndim; d++) g.dxmin = std::fmin(g.dxmin, (desc->hi[d] - desc->lo[d]) / desc->n[d]);
-    g.stride[0] = 1;
-    g.stride[1] = g.p[0];
-    g.stride[2] = (int64_t)g.p[0] * g.p[1];
-    g.vstride = (int64_t)g.p[0] * g.p[1] * g.p[2];
-    g.g1 = 1.0 / (desc->gamma[0] - 1.0);
-    g.g2 = 1.0 / (desc->gamma[1] - 1.0);
-    g.h1 = desc->gamma[0] * desc->pi_inf[0] / (desc->gamma[0] - 1.0);
-    g.h2 = desc->gamma[1] * desc->pi_inf[1] / (desc->gamma[1] - 1.0);
-    g.eps = desc->weno_eps;
-    for (int f = 0; f < 6; f++) g.bc[f] = h->desc.bc[f];
-    set_kapila(g, *desc);
-    g.order = desc->recon == MFC_RECON_WENO3 ? 3 : (desc->recon == MFC_RECON_FIRST_ORDER ? 1 : 5);
-    g.stretched = 0;
-    for (int d = 0; d < desc->ndim; d++) g.stretched |= desc->faces[d] != nullptr;
-    if (g.stretched) g.dxmin = 1.0;   // the reduction then returns max (|u_d| + c)/dx_d
     for (int d = 0; d < 3; d++) h->desc.faces[d] = nullptr;   // the caller's arrays are not kept
     h->cells_padded = g.vstride;
     h->cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
@@ -478,16 +499,17 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
         alloc((void **)&h->faces, (int64_t)3 * (h->nvar + 1) * h->cells_padded * 8);
     }
     if (desc->kernel == MFC_KERNEL_SPLIT) {
-        alloc((void **)&h->lxy, (int64_t)(h->nvar + 1) * h->cells_padded * elem_bytes(h));
-        // characteristic faces: the stage kernels keep the boundary cells'
-        // normal terms (8 values per cell and face) for the boundary pass
+        alloc((void **)&h->lxy, (int64_t)h->nvar * h->cells_padded * elem_bytes(h));
+        // characteristic faces: the x+y kernel applies the x and y faces
+        // itself; the z kernel keeps the normal terms of the z faces' cells
+        // (8 values per cell) for the boundary pass
         int64_t words = 0;
         for (int f = 0; f < 2 * g.ndim; f++) {
             if (g.bc[f] != MFC_BC_CHARACTERISTIC) continue;
-            const int d = f >> 1;
             g.cbc_mask |= 1 << f;
+            if (f < 4) continue;
             g.cbc_off[f] = words;
-            words += 8 * (int64_t)(d == 0 ? g.n[1] : g.n[0]) * (d == 2 ? g.n[1] : g.n[2]);
+            words += 8 * (int64_t)g.n[0] * g.n[1];
         }
         if (words) alloc(&h->cbc_fv, words * elem_bytes(h));
         g.cbc_fv = h->cbc_fv;
@@ -605,7 +627,7 @@ int mfc_max_wavespeed(mfc_grid *h, const void *q, double *smax_host, void *strea
     return MFC_OK;
 }
 
-int mfc_rk3_step(mfc_grid *h, void *qv, double cfl, double dt, void *stream)
+int mfc_rk3_step(mfc_grid *h, void *qv, double cfl, double dt, double *dt_used_dev, void *stream)
 {
     if (bad_handle(h) || !qv) return fail(MFC_E_ARG, "null argument");
     if (!(cfl > 0.0) && !(dt > 0.0)) return fail(MFC_E_ARG, "need cfl > 0 or dt > 0");
@@ -636,6 +658,7 @@ int mfc_rk3_step(mfc_grid *h, void *qv, double cfl, double dt, void *stream)
     if ((st = rhs_dispatch(h, A, q, B, 2, 0.0, dt_dev, s))) return st;
     if (fill && (st = fill_ghosts(h, B, s))) return st;
     if ((st = rhs_dispatch(h, B, q, q, 3, 0.0, dt_dev, s))) return st;
+    if (dt_used_dev) hipLaunchKernelGGL(k_copy_dt, dim3(1), dim3(64), 0, s, h->scalars, dt_used_dev);
     return hip_status(hipGetLastError(), "rk3 step launch");
 }
 
@@ -643,7 +666,7 @@ int mfc_run(mfc_grid *h, void *q, int nsteps, double cfl, double dt, void *strea
 {
     if (nsteps < 0) return fail(MFC_E_ARG, "nsteps must be >= 0");
     for (int n = 0; n < nsteps; n++) {
-        int st = mfc_rk3_step(h, q, cfl, dt, stream);
+        int st = mfc_rk3_step(h, q, cfl, dt, nullptr, stream);
         if (st) return st;
     }
     return MFC_OK;

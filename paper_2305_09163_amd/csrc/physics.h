@@ -47,11 +47,11 @@ struct Grid {
     const double *wcoef[3];
     const double *winv[3];
     // characteristic faces on the split path: bit f of cbc_mask marks face f
-    // (x-, x+, y-, y+, z-, z+); the stage kernels store the finite-volume
-    // terms normal to it of its boundary cells (7 flux differences, then the
-    // normal part of div(u)) at cbc_fv + cbc_off[f] + 8 (c1 + n1 c2), in the
-    // storage type, where c1 < n1 and c2 are the cell's two other
-    // coordinates, the lower dimension first
+    // (x-, x+, y-, y+, z-, z+); the x+y kernel applies the x and y faces to
+    // their boundary cells itself, the z kernel stores the finite-volume
+    // terms normal to a z face of its boundary cells (7 flux differences,
+    // then the normal part of div(u)) at cbc_fv + cbc_off[f] + 8 (x + nx y),
+    // in the storage type, for the boundary pass
     int cbc_mask;
     void *cbc_fv;
     int64_t cbc_off[6];
@@ -97,8 +97,28 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double sqrtT(double a) { return __builtin_sqrt(a); }
-__device__ __forceinline__ float sqrtT(float a) { return __builtin_sqrtf(a); }
+// Square roots of sound speeds squared (positive, normal and finite on
+// physical states; on others the cell has been flagged non-physical and the
+// value is not used).  Double: the hardware reciprocal square root r ~
+// 1/sqrt(a) refined by the coupled Newton-Raphson iteration for
+// s ~ sqrt(a), h ~ 1/(2 sqrt(a)) (one step on (s, h), then two
+// corrections s <- s + h (a - s^2)): the refinement of the full sqrt()
+// sequence without its rescaling of arguments below 2^-767 and its
+// handling of 0 and infinity, half its instructions.  Single: the hardware
+// square root (1 ulp), as in the FP32 reciprocals.
+__device__ __forceinline__ double sqrtT(double a)
+{
+    const double r = __builtin_amdgcn_rsq(a);
+    double s = a * r, h = 0.5 * r;
+    const double e = __builtin_fma(-h, s, 0.5);
+    s = __builtin_fma(s, e, s);
+    h = __builtin_fma(h, e, h);
+    double d = __builtin_fma(-s, s, a);
+    s = __builtin_fma(d, h, s);
+    d = __builtin_fma(-s, s, a);
+    return __builtin_fma(d, h, s);
+}
+__device__ __forceinline__ float sqrtT(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ double fminT(double a, double b) { return __builtin_fmin(a, b); }
 __device__ __forceinline__ float fminT(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ double fmaxT(double a, double b) { return __builtin_fmax(a, b); }

@@ -6,19 +6,27 @@
 //         into LDS once, every cell of the tile plus one halo cell per side is
 //         reconstructed once per direction (WENO5, both face values from one
 //         stencil, Sec. 3.2), the HLLC flux of every face (Sec. 3.2.1) is
-//         computed once and shared by the two cells of the face.  It writes
-//         the x+y flux differences and the x+y face-velocity divergence of
-//         every cell (8 values).
-//   k_z   z direction plus the stage update: one thread per (x, y) column
-//         marches through a chunk of planes with the primitives of five
-//         planes at hand (four in a per-thread LDS ring, the newest in
-//         registers), reconstructs each cell once (both faces) and
-//         solves each z face once, adds the x+y part, forms the alpha1 div(u)
-//         source and the SSP-RK3 combination and writes the stage result.
+//         computed once and shared by the two cells of the face.  Per cell
+//         it forms the x+y flux differences plus the x+y share of the
+//         alpha1 div(u) source (eq. fvmdis) and writes 7 values: that x+y
+//         part L_xy itself, or, when the stage's dt is already known (every
+//         stage after the first, and the first with a given dt), the x+y
+//         part of the SSP-RK3 combination (Sec. 3.4),
+//         ca q^n + cb (q + dt L_xy).
+//   k_z   z direction plus the rest of the stage update: one thread per
+//         (x, y) column marches through a chunk of planes with the
+//         primitives of five planes at hand (four in a per-thread LDS ring,
+//         the newest in registers), reconstructs each cell once (both
+//         faces) and solves each z face once, forms the z flux differences
+//         and the z share of the source, and writes the stage result: the
+//         x+y part plus cb dt L_z (or L_xy + L_z for a bare right-hand side,
+//         q + dt (L_xy + L_z) in the first stage of a CFL step, whose dt is
+//         set between the two launches).
 //
 // Neither kernel carries the other's state, so each fits its registers
-// without spilling; the price is one round trip of 8 values per cell through
-// HBM.  Both kernels are instantiated for FP64 and for the FP32 storage form
+// without spilling; the price is one round trip of 7 values per cell through
+// HBM, and with the combination folded into the x+y pass the z pass reads
+// neither q^n nor its own stage input a second time.  Both kernels are instantiated for FP64 and for the FP32 storage form
 // (T = float; the x+y part is kept in the same type), and with the routed
 // reconstruction (ROUTE = true): every (cell, direction) is first classified by
 // the learned indicator of mlp.h, a whole wavefront at a time, and a smooth
@@ -27,6 +35,7 @@
 // 1 first order; the routed variant is always 5).
 #include <type_traits>
 
+#include "charbc.h"
 #include "internal.h"
 #include "mlp.h"
 
@@ -52,7 +61,17 @@ namespace {
 #endif
 constexpr int TX = MFC_XY_TX, TY = MFC_XY_TY, NT = 256, NOWN = TX * TY;
 static_assert(NOWN <= NT, "one thread per tile cell");
-constexpr int PX = TX + 2 * NG, PY = TY + 2 * NG;
+// Halo width of the reconstruction of order ORDER: WENO5 reads two cells
+// past the face cell (3-cell halos); WENO3 one (2-cell halos, which first
+// order shares: its face problem still needs the neighbour past the face,
+// and the z pass keeps three planes so that the updated cell is in the
+// window).  OFF is where the stencil of the cell at plane index h starts,
+// relative to h - (H - 1): 0 for WENO5 and WENO3, 1 for first order.
+template <int ORDER>
+constexpr int kHalo = ORDER == 5 ? 3 : 2;
+template <int ORDER>
+constexpr int kOff = kHalo<ORDER> - 1 - (ORDER - 1) / 2;
+static_assert(kHalo<5> <= NG && kHalo<3> <= NG, "halos fit the ghost layers");
 constexpr int NPX = (TX + 2) * TY;  // x reconstructions: cells -1 .. TX of every row
 constexpr int NPY = TX * (TY + 2);  // y reconstructions: rows -1 .. TY of every column
 static_assert(NPX <= NT && NPY <= NT, "one reconstruction per thread and direction");
@@ -63,7 +82,6 @@ constexpr int NP = NPX > NPY ? NPX : NPY;
 constexpr int NFX = (TX + 2) * (TY - 1) + TX + 1;
 constexpr int NFY = TX * (TY + 1);
 constexpr int NF = NFX > NFY ? NFX : NFY;
-constexpr int NHALO = 2 * NG * (TX + TY);
 constexpr int kPlanesXY = MFC_XY_PLANES;  // planes per k_xy workgroup
 #ifndef MFC_Z_Y
 #define MFC_Z_Y 4
@@ -119,15 +137,50 @@ __device__ __forceinline__ int bc_cell(int i, int n, int lo, int hi)
     return i;
 }
 
+// Both face values of a cell from the ORDER values of its stencil, starting
+// at st with stride s (WENO5, WENO3 or first order, Sec. 3.2).
+template <int ORDER, class T>
+__device__ __forceinline__ void recon_at(const T *st, int s, T eps, T &plus, T &minus)
+{
+    if constexpr (ORDER == 5) {
+        weno5_pair(st[0], st[s], st[2 * s], st[3 * s], st[4 * s], eps, plus, minus);
+    } else if constexpr (ORDER == 3) {
+        weno3_pair(st[0], st[s], st[2 * s], eps, plus, minus);
+    } else {
+        plus = st[0];
+        minus = st[0];
+    }
+}
+
+// Characteristic rates (charbc.h) of the boundary cell at plane position
+// (r, c) of an LDS plane tile, on face SIDE of dimension D (0: x, 1: y),
+// from the cell and the next two cells into the domain.
+template <int D, int SIDE, class T, int PY, int PX>
+__device__ __forceinline__ bool plane_char_rate(const Grid &g, const T (&pl)[7][PY][PX], int r, int c, T inv_dx,
+                                                T *rate)
+{
+    constexpr int sg = SIDE == 0 ? 1 : -1;
+    T W[3][7];
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+#pragma unroll
+        for (int v = 0; v < 7; v++) W[j][v] = D == 0 ? pl[v][r][c + sg * j] : pl[v][r + sg * j][c];
+    return char_rate<3, D, SIDE, T>(g, W[0], W[1], W[2], inv_dx, rate);
+}
+
 // Load and convert cell (i, j, bc_cell(k)) of a column (i, j interior).
+template <class T>
+__device__ __forceinline__ void load_cons_z(const Grid &g, const T *__restrict__ q, int i, int j, int k, T *qc)
+{
+    const int64_t c = offset(g, i, j, bc_cell(k, g.n[2], g.bc[4], g.bc[5]));
+#pragma unroll
+    for (int v = 0; v < 7; v++) qc[v] = q[v * g.vstride + c];
+}
 template <class T>
 __device__ __forceinline__ bool load_prim_z(const Grid &g, const T *__restrict__ q, int i, int j, int k, T *w)
 {
-    constexpr int NV = 7;
-    const int64_t c = offset(g, i, j, bc_cell(k, g.n[2], g.bc[4], g.bc[5]));
-    T qc[NV];
-#pragma unroll
-    for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
+    T qc[7];
+    load_cons_z<T>(g, q, i, j, k, qc);
     return cons_to_prim<3, T>(g, qc, w);
 }
 
@@ -157,12 +210,27 @@ struct RouteLds {
 template <class T, bool ROUTE, bool STRETCH = false>
 constexpr int kXYWaves = ROUTE ? 2 : (STRETCH ? (sizeof(T) == 8 ? 2 : 4) : (sizeof(T) == 8 ? 3 : MFC_XY_WAVES32));
 
+// The x+y pass holds the operands of its part of the stage combination in
+// registers from the start of each plane (FP64: their latency then overlaps
+// the plane's work, measured faster), or loads them at its end (FP32, whose
+// five wavefronts per SIMD leave no registers for them).
+#ifndef MFC_XY_HOLD64
+#define MFC_XY_HOLD64 0
+#endif
+template <class T>
+constexpr bool kHoldFold = sizeof(T) == 8 ? MFC_XY_HOLD64 : 0;
+
 template <class T, bool ROUTE, int ORDER, bool STRETCH, bool KEEP>
 __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
-    k_xy(Grid g, const T *__restrict__ q, T *__restrict__ lxy, int *__restrict__ flag,
-         const float *__restrict__ mlpw, float logit_tau, T sqrt_eps, double *__restrict__ smax_partial)
+    k_xy(Grid g, const T *__restrict__ q, const T *q0, T *__restrict__ lxy, int *__restrict__ flag,
+         const float *__restrict__ mlpw, float logit_tau, T sqrt_eps, double *__restrict__ smax_partial,
+         int mode, int fold, double dt, const double *__restrict__ dt_dev)
 {
     constexpr int NV = 7;
+    // plane tile with halos of this order's width H; a stencil of ORDER
+    // values of the cell at plane column (row) h starts at h - (H - 1) + OFF
+    constexpr int H = kHalo<ORDER>, OFF = kOff<ORDER>;
+    constexpr int PX = TX + 2 * H, PY = TY + 2 * H, NHALO = 2 * H * (TX + TY);
     using R = RouteLds<T, ROUTE>;
     __shared__ T s_plane[NV][PY][PX];
     __shared__ T s_minus[NV][NP];                    // - face value of every reconstruction
@@ -170,6 +238,11 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
     __shared__ __align__(16) typename R::P s_mlp;
     __shared__ __align__(16) uint16_t s_feat_own[R::own_words];
     const T eps = T(g.eps);
+    // stage combination ca q^n + cb (q + dt L) of the SSP-RK3 stage `mode`
+    // (1, 2, 3), formed here for the x+y part when `fold` is set
+    const T hdt = T(fold ? (dt_dev ? *dt_dev : dt) : 0.0);
+    const T ca = T(mode == 2 ? 0.75 : (mode == 3 ? 1.0 / 3.0 : 0.0));
+    const T cb = T(mode == 2 ? 0.25 : (mode == 3 ? 2.0 / 3.0 : 1.0));
     const int lane = threadIdx.x % 64;
     uint16_t *scratch = (R::in_flux ? (uint16_t *)&s_flux[0][0] : s_feat_own) + (threadIdx.x / 64) * 64 * 16;
     if constexpr (ROUTE) mlp::stage_params(s_mlp, nullptr, mlpw, threadIdx.x, NT);  // visible after the first barrier
@@ -180,7 +253,7 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
     tile_of_block(bx, by, bz);
     const int x0 = bx * TX, y0 = by * TY;
     const int z0 = bz * kPlanesXY, z1 = min(z0 + kPlanesXY, g.n[2]);
-    const int xmax = g.n[0] + NG - 1, ymax = g.n[1] + NG - 1;
+    const int xmax = g.n[0] + H - 1, ymax = g.n[1] + H - 1;
     const int gx = x0 + tx, gy = y0 + ty;
     const bool cell = tid < NOWN;                       // this thread has a tile cell
     const bool own = cell && gx < g.n[0] && gy < g.n[1];
@@ -192,21 +265,21 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
     static_assert(NHALO <= NT, "one halo cell per thread");
     const bool halo = tid < NHALO;
     int hli = 0, hlj = 0;
-    if (tid < 2 * NG * TY) {
-        const int c = tid % (2 * NG), row = tid / (2 * NG);
-        hli = c < NG ? c : TX + c;
-        hlj = row + NG;
+    if (tid < 2 * H * TY) {
+        const int c = tid % (2 * H), row = tid / (2 * H);
+        hli = c < H ? c : TX + c;
+        hlj = row + H;
     } else {
-        const int h2 = tid - 2 * NG * TY;
+        const int h2 = tid - 2 * H * TY;
         const int c = h2 % TX, r = h2 / TX;
-        hli = c + NG;
-        hlj = r < NG ? r : TY + r;
+        hli = c + H;
+        hlj = r < H ? r : TY + r;
     }
     // cells past a ragged tile edge load a duplicate whose results are discarded
     const int ox = bc_cell(min(gx, xmax), g.n[0], g.bc[0], g.bc[1]);
     const int oy = bc_cell(min(gy, ymax), g.n[1], g.bc[2], g.bc[3]);
-    const int hx = bc_cell(min(x0 + hli - NG, xmax), g.n[0], g.bc[0], g.bc[1]);
-    const int hy = bc_cell(min(y0 + hlj - NG, ymax), g.n[1], g.bc[2], g.bc[3]);
+    const int hx = bc_cell(min(x0 + hli - H, xmax), g.n[0], g.bc[0], g.bc[1]);
+    const int hy = bc_cell(min(y0 + hlj - H, ymax), g.n[1], g.bc[2], g.bc[3]);
     T qo[NV], qh[NV];
     auto fetch = [&](int k) {
         if (cell) {
@@ -247,11 +320,11 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
                 T w[NV];
                 bad |= cons_to_prim<3, T>(g, qo, w);
 #pragma unroll
-                for (int v = 0; v < NV; v++) s_plane[v][ty + NG][tx + NG] = w[v];
+                for (int v = 0; v < NV; v++) s_plane[v][ty + H][tx + H] = w[v];
                 if (smax_partial && own) {
                     double Gam, Pi;
                     mixture<double>(g, double(w[6]), Gam, Pi);
-                    const double cs = __builtin_sqrt(sound2<double>(Gam, Pi, double(w[0]) + double(w[1]), double(w[5])));
+                    const double cs = sqrtT(sound2<double>(Gam, Pi, double(w[0]) + double(w[1]), double(w[5])));
                     if constexpr (STRETCH) {   // non-uniform cells: the largest (|u_d| + c)/dx_d
                         const int ci[3] = {gx, gy, k};
 #pragma unroll
@@ -271,6 +344,20 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
             }
         }
         __syncthreads();
+        // operands of the x+y part of the stage combination, held from here
+        // to the end of the plane so that the q^n load overlaps its work:
+        // the cell's stage input (before the next plane's fetch replaces it)
+        // and q^n
+        T qc[NV], q0c[NV];
+        if (kHoldFold<T> && fold && own) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) qc[v] = qo[v];
+            if (mode != 1) {
+                const int64_t c = offset(g, gx, gy, k);
+#pragma unroll
+                for (int v = 0; v < NV; v++) q0c[v] = q0[v * g.vstride + c];
+            }
+        }
         if (k + 1 < z1) fetch(k + 1);
 
         // ---- x: thread p reconstructs cell p % (TX + 2) - 1 of row p / (TX + 2)
@@ -284,18 +371,18 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
             bool lin = false;
             if constexpr (ROUTE) {  // whole wavefronts classify together
                 if (__ballot(valid))
-                    lin = mlp::smooth_stencil<T>(s_mlp, scratch, &s_plane[6][row + NG][c], &s_plane[0][row + NG][c],
-                                                 &s_plane[1][row + NG][c], &s_plane[5][row + NG][c], 1, sqrt_eps,
+                    lin = mlp::smooth_stencil<T>(s_mlp, scratch, &s_plane[6][row + H][c], &s_plane[0][row + H][c],
+                                                 &s_plane[1][row + H][c], &s_plane[5][row + H][c], 1, sqrt_eps,
                                                  logit_tau, lane);
             }
             if (valid) {
                 const T *cl = kLdsCoef && g.wcoef[0] ? &s_cx[c * kStretchCoef] : nullptr;
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
-                    const T *st = &s_plane[v][row + NG][c];
+                    const T *st = &s_plane[v][row + H][c + OFF];
                     if (ROUTE && lin) linear5_pair<T>(st[0], st[1], st[2], st[3], st[4], wP[v], s_minus[v][p]);
                     else if (kLdsCoef && cl) weno5_nonuniform_pair<T>(cl, st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
-                    else recon_pair<ORDER, T>(st[0], st[1], st[2], st[3], st[4], eps, wP[v], s_minus[v][p]);
+                    else recon_at<ORDER, T>(st, 1, eps, wP[v], s_minus[v][p]);
                 }
             }
         }
@@ -322,9 +409,17 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
 #pragma unroll
             for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * idx;
             divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * idx;
-            if (KEEP && (g.cbc_mask & 3)) {   // characteristic x faces keep the boundary cells' x terms
-                if (own && gx == 0 && (g.cbc_mask & 1)) store_normal_terms<0, T>(g, gy, g.n[1], k, L, divu);
-                if (own && gx == g.n[0] - 1 && (g.cbc_mask & 2)) store_normal_terms<1, T>(g, gy, g.n[1], k, L, divu);
+            if (KEEP && (g.cbc_mask & 3) && own) {
+                // the boundary cell of a characteristic x face takes the
+                // characteristic rates in place of its x terms (Sec. 3.3),
+                // from itself and the next two cells into the domain
+                if (gx == 0 && (g.cbc_mask & 1)) {
+                    bad |= plane_char_rate<0, 0>(g, s_plane, ty + H, tx + H, idx, L);
+                    divu = T(0);
+                } else if (gx == g.n[0] - 1 && (g.cbc_mask & 2)) {
+                    bad |= plane_char_rate<0, 1>(g, s_plane, ty + H, tx + H, idx, L);
+                    divu = T(0);
+                }
             }
         }
         // ---- y: thread p reconstructs row p / TX - 1 of column p % TX and
@@ -334,7 +429,7 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
             const int p = tid;
             const bool valid = p < NPY;
             const int pc = valid ? p : NPY - 1;
-            const int li = pc % TX + NG, r = pc / TX;
+            const int li = pc % TX + H, r = pc / TX;
             bool lin = false;
             if constexpr (ROUTE) {
                 if (__ballot(valid))
@@ -353,8 +448,7 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
                         weno5_nonuniform_pair<T>(cl, s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
                                                  s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, wP[v], s_minus[v][p]);
                     else
-                        recon_pair<ORDER, T>(s_plane[v][r][li], s_plane[v][r + 1][li], s_plane[v][r + 2][li],
-                                   s_plane[v][r + 3][li], s_plane[v][r + 4][li], eps, wP[v], s_minus[v][p]);
+                        recon_at<ORDER, T>(&s_plane[v][r + OFF][li], PX, eps, wP[v], s_minus[v][p]);
                 }
             }
         }
@@ -375,23 +469,48 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
         __syncthreads();
         if (cell) {
             const int f = ty * TX + tx;
-            if (KEEP && (g.cbc_mask & 12)) {   // characteristic y faces keep the boundary cells' y terms
-                T Ly[NV];
+            T Ly[NV];
 #pragma unroll
-                for (int v = 0; v < NV; v++) Ly[v] = (s_flux[v][f] - s_flux[v][f + TX]) * idy;
-                const T dy = (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
-                if (own && gy == 0 && (g.cbc_mask & 4)) store_normal_terms<2, T>(g, gx, g.n[0], k, Ly, dy);
-                if (own && gy == g.n[1] - 1 && (g.cbc_mask & 8)) store_normal_terms<3, T>(g, gx, g.n[0], k, Ly, dy);
+            for (int v = 0; v < NV; v++) Ly[v] = (s_flux[v][f] - s_flux[v][f + TX]) * idy;
+            T dy = (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
+            if (KEEP && (g.cbc_mask & 12) && own) {   // characteristic y faces, as for x
+                if (gy == 0 && (g.cbc_mask & 4)) {
+                    bad |= plane_char_rate<1, 0>(g, s_plane, ty + H, tx + H, idy, Ly);
+                    dy = T(0);
+                } else if (gy == g.n[1] - 1 && (g.cbc_mask & 8)) {
+                    bad |= plane_char_rate<1, 1>(g, s_plane, ty + H, tx + H, idy, Ly);
+                    dy = T(0);
+                }
             }
 #pragma unroll
-            for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * idy;
-            divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
+            for (int v = 0; v < NV; v++) L[v] += Ly[v];
+            divu += dy;
         }
         if (own) {
             const int64_t c = offset(g, gx, gy, k);
+            // the x+y share of the alpha1 row's source, from the cell's own
+            // primitives (only this thread writes its cell's LDS slots)
+            L[NV - 1] += alpha_source<T>(g, s_plane[NV - 1][ty + H][tx + H], s_plane[NV - 2][ty + H][tx + H]) * divu;
+            if (fold) {
+                if constexpr (!kHoldFold<T>) {   // loaded here instead (registers are scarcer)
 #pragma unroll
-            for (int v = 0; v < NV; v++) lxy[v * g.vstride + c] = L[v];
-            lxy[NV * g.vstride + c] = divu;
+                    for (int v = 0; v < NV; v++) qc[v] = q[v * g.vstride + c];
+                    if (mode != 1) {
+#pragma unroll
+                        for (int v = 0; v < NV; v++) q0c[v] = q0[v * g.vstride + c];
+                    }
+                }
+                if (mode != 1) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++) lxy[v * g.vstride + c] = ca * q0c[v] + cb * (qc[v] + hdt * L[v]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; v++) lxy[v * g.vstride + c] = qc[v] + hdt * L[v];
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; v++) lxy[v * g.vstride + c] = L[v];
+            }
         }
         // the next plane overwrites s_plane (last read before the y-face
         // barrier), s_minus and s_flux only after one and two more barriers
@@ -439,6 +558,11 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
 #ifndef MFC_Z_RING_ROUTE
 #define MFC_Z_RING_ROUTE 1
 #endif
+// odd z chunks marched downward (see k_z)
+#ifndef MFC_Z_ALT
+#define MFC_Z_ALT 0
+#endif
+
 template <class T>
 constexpr int kZWaves = sizeof(T) == 8 ? MFC_Z_WAVES64 : MFC_Z_WAVES32;
 template <class T>
@@ -449,13 +573,19 @@ constexpr int kRing = ROUTE ? MFC_Z_RING_ROUTE : MFC_Z_RING;
 static_assert(kRing<false> >= 1 && kRing<false> <= 4 && kRing<true> >= 1 && kRing<true> <= 4,
               "one to four planes in the ring");
 
-template <class T, bool ROUTE, int ORDER, bool STRETCH, bool KEEP>
+// REREAD: the first stage of a CFL step, whose x+y pass could not form its
+// part of the stage combination (dt unknown then): out = q + dt (L_xy + L_z),
+// reading the stage input again.  Otherwise out = (x+y part) + s L_z with
+// s = cb dt (a folded stage) or 1 (a bare right-hand side).
+template <class T, bool ROUTE, int ORDER, bool STRETCH, bool KEEP, bool REREAD>
 __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
-    k_z(Grid g, const T *__restrict__ q, const T *q0, T *out, const T *__restrict__ lxy, int mode, double dt,
+    k_z(Grid g, const T *__restrict__ q, T *__restrict__ out, const T *__restrict__ lxy, int mode, double dt,
         const double *__restrict__ dt_dev, int *__restrict__ flag, const float *__restrict__ mlpw, float logit_tau,
         T sqrt_eps)
 {
-    constexpr int kRing = mfc::kRing<ROUTE>, kZReg = 5 - kRing;
+    // window of W = 2H - 1 planes; the kRing oldest in the LDS ring
+    constexpr int H = kHalo<ORDER>, OFF = kOff<ORDER>, W = 2 * H - 1;
+    constexpr int kRing = mfc::kRing<ROUTE> < W - 1 ? mfc::kRing<ROUTE> : W - 1, kZReg = W - kRing;
     constexpr int NV = 7, A = 6, NZT = kZX * kZY;
     const T eps = T(g.eps), idz_u = T(g.inv_dx[2]);
     int bx, by, bz;
@@ -480,128 +610,157 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
     const int lane = threadIdx.x % 64, t = threadIdx.x;
     const int z0 = bz * kLZ<T>, z1 = min(z0 + kLZ<T>, g.n[2]);
     const T hdt = T(mode ? (dt_dev ? *dt_dev : dt) : 0.0);
-    const T ca = T(mode == 1 ? 0.0 : (mode == 2 ? 0.75 : 1.0 / 3.0));
-    const T cb = T(mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0));
+    const T cb = T(mode == 2 ? 0.25 : (mode == 3 ? 2.0 / 3.0 : 1.0));
+    const T sz = mode ? cb * hdt : T(1);   // weight of L_z in the result
     bool bad = false;
 
-    // window of the reconstruction of cell k+1 (planes k-1 .. k+3): plane
-    // k-1+j in ring slot rs[j] for j < kRing, else in zr[j - kRing]
+    // The chunk is marched upward (S = +1) or downward (S = -1), alternately
+    // from chunk to chunk, so that two neighbouring chunks read the planes
+    // they share at about the same time (both at the end of their marches,
+    // or both at the start), while those planes are still in L2.  A cell's
+    // arithmetic is the same either way: the reconstruction of a cell from
+    // its five planes in increasing z, each face solved once with its lower
+    // cell on the left.
+    //
+    // At step k (the cell updated), the window holds the W planes around
+    // cell k + S: planes k + S - (H - 1) .. k + S + (H - 1) (for WENO5
+    // k - 1 .. k + 3 if S = +1, k - 3 .. k + 1 if S = -1).  Window position
+    // i (0 = oldest plane, W - 1 = the newest, plane k + S H) is ring slot
+    // rs[i] for i < kRing, else zr[i - kRing]; window index j (0 = lowest z)
+    // is position j (S = +1) or W - 1 - j (S = -1).
     int rs[kRing];
     T zr[kZReg][NV];
-    T pk[NV];      // cell k reconstructed at its + face
-    T Fz[NV + 1];  // flux and face velocity at k-1/2
+    T ck[NV];      // cell k at its face toward the march: + face (S = +1), - face (S = -1)
+    T Fz[NV + 1];  // flux and face velocity at the face of cell k behind the march
+    auto march = [&](auto dir) {
+        constexpr int S = decltype(dir)::value;
+        auto win = [&](int j, int v) -> T {
+            const int i = S > 0 ? j : W - 1 - j;
+            return i < kRing ? s_ring[rs[i]][v][t] : zr[i - kRing][v];
+        };
+        const int kfirst = S > 0 ? z0 - 2 : z1 + 1;
+        // the W - 1 oldest planes of the first window: plane kfirst + S + S (i - (H - 1))
 #pragma unroll
-    for (int j = 0; j < kRing; j++) {
-        rs[j] = j;
-        bad |= load_prim_z<T>(g, q, gx, gy, z0 - 3 + j, zr[kZReg - 1]);
+        for (int i = 0; i < kRing; i++) {
+            rs[i] = i;
+            bad |= load_prim_z<T>(g, q, gx, gy, kfirst + S * (i + 2 - H), zr[kZReg - 1]);
 #pragma unroll
-        for (int v = 0; v < NV; v++) s_ring[j][v][t] = zr[kZReg - 1][v];
-    }
+            for (int v = 0; v < NV; v++) s_ring[i][v][t] = zr[kZReg - 1][v];
+        }
 #pragma unroll
-    for (int j = kRing; j < 4; j++) bad |= load_prim_z<T>(g, q, gx, gy, z0 - 3 + j, zr[j - kRing]);
+        for (int i = kRing; i < W - 1; i++) bad |= load_prim_z<T>(g, q, gx, gy, kfirst + S * (i + 2 - H), zr[i - kRing]);
 
-    auto win = [&](int j, int v) -> T { return j < kRing ? s_ring[rs[j]][v][t] : zr[j - kRing][v]; };
-    for (int k = z0 - 2; k < z1; k++) {
-        bad |= load_prim_z<T>(g, q, gx, gy, k + 3, zr[kZReg - 1]);
-        // FP32: the operands of the stage update of cell k are loaded before
-        // the reconstruction so that their latency overlaps it (the FP64
-        // kernel has no registers to spare for them and loads them late)
-        T lx[NV + 1], qa[NV], qb[NV];
-        if constexpr (kZEarly<T>) {
-            if (k >= z0 && own) {
-                const int64_t c = offset(g, gx, gy, k);
+        const int steps = z1 - z0 + 2;
+        for (int st = 0; st < steps; st++) {
+            const int k = kfirst + S * st;
+            bad |= load_prim_z<T>(g, q, gx, gy, k + H * S, zr[kZReg - 1]);
+            // FP32: the operands of the stage update of cell k are loaded before
+            // the reconstruction so that their latency overlaps it (the FP64
+            // kernel has no registers to spare for them and loads them late)
+            T lx[NV], qb[NV];
+            auto load_update = [&](int64_t c) {
 #pragma unroll
-                for (int v = 0; v <= NV; v++) lx[v] = lxy[v * g.vstride + c];
-                if (mode != 0) {
+                for (int v = 0; v < NV; v++) lx[v] = lxy[v * g.vstride + c];
+                if constexpr (REREAD) {
 #pragma unroll
-                    for (int v = 0; v < NV; v++) {
-                        qa[v] = q0[v * g.vstride + c];
-                        qb[v] = q[v * g.vstride + c];
-                    }
+                    for (int v = 0; v < NV; v++) qb[v] = q[v * g.vstride + c];
                 }
-            }
-        }
-        T pn[NV], mn[NV], Fzn[NV + 1];
-        bool lin = false;
-        if constexpr (ROUTE) {
-            T av[5], rv[5], pv[5];
-#pragma unroll
-            for (int j = 0; j < 5; j++) {
-                av[j] = win(j, A);
-                rv[j] = win(j, 0) + win(j, 1);
-                pv[j] = win(j, 5);
-            }
-            uint16_t f[16];
-            mlp::features<T>(av, rv, pv, sqrt_eps, f);
-            lin = mlp::smooth_wave(s_mlp, scratch, f, logit_tau, lane);
-        }
-        CoefRegs<T> cf;   // cell k+1 of this window
-        if constexpr (STRETCH && ORDER == 5) load_coefs<T>(coef_row(g, 2, k + 1), cf);
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-            const T w0 = win(0, v), w1 = win(1, v), w2 = win(2, v), w3 = win(3, v), w4 = win(4, v);
-            if (ROUTE && lin) linear5_pair<T>(w0, w1, w2, w3, w4, pn[v], mn[v]);
-            else if (STRETCH && ORDER == 5) recon_cell<ORDER, T>(cf, w0, w1, w2, w3, w4, eps, pn[v], mn[v]);
-            else recon_pair<ORDER, T>(w0, w1, w2, w3, w4, eps, pn[v], mn[v]);
-        }
-        if (k >= z0 - 1) bad |= hllc<3, 2, T>(g, pk, mn, Fzn, Fzn[NV]);
-#pragma unroll
-        for (int v = 0; v < NV; v++) pk[v] = pn[v];
-        if (k >= z0 && own) {
-            const int64_t c = offset(g, gx, gy, k);
-            const T idz = STRETCH ? T(inv_width(g, 2, k)) : idz_u;
-            T L[NV], divu;
-            if (KEEP && (g.cbc_mask & 48)) {   // characteristic z faces keep the boundary cells' z terms
-                T Lz[NV];
-#pragma unroll
-                for (int v = 0; v < NV; v++) Lz[v] = (Fz[v] - Fzn[v]) * idz;
-                const T dz = (Fzn[NV] - Fz[NV]) * idz;
-                if (k == 0 && (g.cbc_mask & 16)) store_normal_terms<4, T>(g, gx, g.n[0], gy, Lz, dz);
-                if (k == g.n[2] - 1 && (g.cbc_mask & 32)) store_normal_terms<5, T>(g, gx, g.n[0], gy, Lz, dz);
-            }
+            };
+            const bool upd = st >= 2 && own;   // cell k is in the chunk
             if constexpr (kZEarly<T>) {
-#pragma unroll
-                for (int v = 0; v < NV; v++) L[v] = lx[v] + (Fz[v] - Fzn[v]) * idz;
-                divu = lx[NV] + (Fzn[NV] - Fz[NV]) * idz;
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; v++) L[v] = lxy[v * g.vstride + c] + (Fz[v] - Fzn[v]) * idz;
-                divu = lxy[NV * g.vstride + c] + (Fzn[NV] - Fz[NV]) * idz;
+                if (upd) load_update(offset(g, gx, gy, k));
             }
-            L[A] += alpha_source<T>(g, win(1, A), win(1, A - 1)) * divu;
-            if (mode == 0) {
+            T pn[NV], mn[NV], Fzn[NV + 1];
+            bool lin = false;
+            if constexpr (ROUTE) {
+                T av[5], rv[5], pv[5];
 #pragma unroll
-                for (int v = 0; v < NV; v++) out[v * g.vstride + c] = L[v];
-            } else {
-                if constexpr (!kZEarly<T>) {
-                    // every operand before the first store: out may alias q0
-                    // (the last stage updates q^n in place), so a store
-                    // would otherwise hold back the next variable's loads
-#pragma unroll
-                    for (int v = 0; v < NV; v++) {
-                        qa[v] = q0[v * g.vstride + c];
-                        qb[v] = q[v * g.vstride + c];
-                    }
+                for (int j = 0; j < 5; j++) {
+                    av[j] = win(j, A);
+                    rv[j] = win(j, 0) + win(j, 1);
+                    pv[j] = win(j, 5);
                 }
-#pragma unroll
-                for (int v = 0; v < NV; v++) out[v * g.vstride + c] = ca * qa[v] + cb * (qb[v] + hdt * L[v]);
+                uint16_t f[16];
+                mlp::features<T>(av, rv, pv, sqrt_eps, f);
+                lin = mlp::smooth_wave(s_mlp, scratch, f, logit_tau, lane);
             }
+            CoefRegs<T> cf;   // cell k + S of this window
+            if constexpr (STRETCH && ORDER == 5) load_coefs<T>(coef_row(g, 2, k + S), cf);
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                T st[ORDER];   // the stencil of cell k + S, lowest z first
+#pragma unroll
+                for (int j = 0; j < ORDER; j++) st[j] = win(OFF + j, v);
+                if constexpr (ORDER == 5) {
+                    if (ROUTE && lin) linear5_pair<T>(st[0], st[1], st[2], st[3], st[4], pn[v], mn[v]);
+                    else if (STRETCH) recon_cell<ORDER, T>(cf, st[0], st[1], st[2], st[3], st[4], eps, pn[v], mn[v]);
+                    else recon_at<ORDER, T>(st, 1, eps, pn[v], mn[v]);
+                } else {
+                    recon_at<ORDER, T>(st, 1, eps, pn[v], mn[v]);
+                }
+            }
+            // the face between cells k and k + S (the first step's is not needed)
+            if (st >= 1) {
+                if constexpr (S > 0) bad |= hllc<3, 2, T>(g, ck, mn, Fzn, Fzn[NV]);
+                else bad |= hllc<3, 2, T>(g, pn, ck, Fzn, Fzn[NV]);
+            }
+            // The face's values as rounded, before any use: a value that
+            // ends in a product (alpha1 u_face, u_face itself) would
+            // otherwise be fused into the flux difference of this step's
+            // cell but enter the next cell's difference rounded, and the
+            // face would not cancel between the two (a uniform state would
+            // not give a zero right-hand side).
+#pragma unroll
+            for (int v = 0; v <= NV; v++) __asm__ volatile("" : "+v"(Fzn[v]));
+#pragma unroll
+            for (int v = 0; v < NV; v++) ck[v] = S > 0 ? pn[v] : mn[v];
+            if (upd) {
+                const int64_t c = offset(g, gx, gy, k);
+                const T idz = STRETCH ? T(inv_width(g, 2, k)) : idz_u;
+                // fluxes at k - 1/2 and k + 1/2
+                const T *Flo = S > 0 ? Fz : Fzn, *Fhi = S > 0 ? Fzn : Fz;
+                T L[NV], divu;
+                if (KEEP && (g.cbc_mask & 48)) {   // characteristic z faces keep the boundary cells' z terms
+                    T Lz[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; v++) Lz[v] = (Flo[v] - Fhi[v]) * idz;
+                    const T dz = (Fhi[NV] - Flo[NV]) * idz;
+                    if (k == 0 && (g.cbc_mask & 16)) store_normal_terms<4, T>(g, gx, g.n[0], gy, Lz, dz);
+                    if (k == g.n[2] - 1 && (g.cbc_mask & 32)) store_normal_terms<5, T>(g, gx, g.n[0], gy, Lz, dz);
+                }
+                // every operand before the first store (the FP64 kernel loads
+                // them here, having no registers to spare earlier)
+                if constexpr (!kZEarly<T>) load_update(c);
+#pragma unroll
+                for (int v = 0; v < NV; v++) L[v] = (Flo[v] - Fhi[v]) * idz;
+                divu = (Fhi[NV] - Flo[NV]) * idz;
+                L[A] += alpha_source<T>(g, win(H - 1 - S, A), win(H - 1 - S, A - 1)) * divu;   // the z share of the source
+                if constexpr (REREAD) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++) out[v * g.vstride + c] = qb[v] + hdt * (lx[v] + L[v]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; v++) out[v * g.vstride + c] = lx[v] + sz * L[v];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v <= NV; v++) Fz[v] = Fzn[v];
+            // shift the window: the oldest plane in registers replaces the
+            // oldest plane of the ring
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                s_ring[rs[0]][v][t] = zr[0][v];
+#pragma unroll
+                for (int j = 0; j + 1 < kZReg; j++) zr[j][v] = zr[j + 1][v];
+            }
+            const int r = rs[0];
+#pragma unroll
+            for (int j = 0; j + 1 < kRing; j++) rs[j] = rs[j + 1];
+            rs[kRing - 1] = r;
         }
-#pragma unroll
-        for (int v = 0; v <= NV; v++) Fz[v] = Fzn[v];
-        // shift the window: plane k+kRing-1+1 (the oldest in registers)
-        // replaces plane k-1 in the ring
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-            s_ring[rs[0]][v][t] = zr[0][v];
-#pragma unroll
-            for (int j = 0; j + 1 < kZReg; j++) zr[j][v] = zr[j + 1][v];
-        }
-        const int r = rs[0];
-#pragma unroll
-        for (int j = 0; j + 1 < kRing; j++) rs[j] = rs[j + 1];
-        rs[kRing - 1] = r;
-    }
+    };
+    if (MFC_Z_ALT && (bz & 1)) march(std::integral_constant<int, -1>{});
+    else march(std::integral_constant<int, 1>{});
     if (bad) atomicOr(flag, 1);
 }
 
@@ -620,13 +779,22 @@ int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
     T *lxy = (T *)h->lxy;
     const T se = T(__builtin_sqrt(g.eps));
     double *partial = cfl > 0.0 ? h->partial : nullptr;
+    // the x+y pass forms its part of the stage combination whenever the
+    // stage's dt is known before it runs (not in the first stage of a CFL
+    // step, whose dt is set from that pass's wave-speed maxima)
+    const int fold = mode != 0 && !partial;
     timing_begin(h, s);
-    hipLaunchKernelGGL((k_xy<T, ROUTE, ORDER, STRETCH, KEEP>), gxy, dim3(NT), 0, s, g, q, lxy, h->flag, h->mlp, h->logit_tau, se, partial);
+    hipLaunchKernelGGL((k_xy<T, ROUTE, ORDER, STRETCH, KEEP>), gxy, dim3(NT), 0, s, g, q, q0, lxy, h->flag, h->mlp,
+                       h->logit_tau, se, partial, mode, fold, dt, dt_dev);
     timing_end(h, s);
     if (partial) launch_step_begin(h, partial, (int)split_xy_blocks(g), cfl, 0.0, s);
     timing_begin(h, s, 1);
-    hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH, KEEP>), gz, dim3(kZX * kZY), 0, s, g, q, q0, out, lxy, mode, dt, dt_dev, h->flag, h->mlp,
-                       h->logit_tau, se);
+    if (mode != 0 && !fold)
+        hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH, KEEP, true>), gz, dim3(kZX * kZY), 0, s, g, q, out, lxy, mode,
+                           dt, dt_dev, h->flag, h->mlp, h->logit_tau, se);
+    else
+        hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH, KEEP, false>), gz, dim3(kZX * kZY), 0, s, g, q, out, lxy, mode,
+                           dt, dt_dev, h->flag, h->mlp, h->logit_tau, se);
     timing_end(h, s, 1);
     return hip_status(hipGetLastError(), "split right-hand side launch");
 }

@@ -63,7 +63,7 @@ _SIGNATURES = {
     "mfc_fill_ghosts": [_VP, _VP, _VP],
     "mfc_rhs": [_VP, _VP, _VP, _VP],
     "mfc_max_wavespeed": [_VP, _VP, ctypes.POINTER(ctypes.c_double), _VP],
-    "mfc_rk3_step": [_VP, _VP, ctypes.c_double, ctypes.c_double, _VP],
+    "mfc_rk3_step": [_VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP],
     "mfc_run": [_VP, _VP, ctypes.c_int, ctypes.c_double, ctypes.c_double, _VP],
     "mfc_time": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _VP],
     "mfc_reset_time": [_VP, _VP],
@@ -215,8 +215,11 @@ def mfc_max_wavespeed(h, q, stream=None) -> float:
     return s.value
 
 
-def mfc_rk3_step(h, q, cfl: float = 0.0, dt: float = 0.0, stream=None):
-    _check(lib().mfc_rk3_step(h, _ptr(q), cfl, dt, _stream(stream)), "mfc_rk3_step")
+def mfc_rk3_step(h, q, cfl: float = 0.0, dt: float = 0.0, dt_used=None, stream=None):
+    """One SSP-RK3 step; dt_used: optional device float64 tensor that receives
+    the step size taken."""
+    _check(lib().mfc_rk3_step(h, _ptr(q), cfl, dt, _ptr(dt_used) if dt_used is not None else None,
+                              _stream(stream)), "mfc_rk3_step")
 
 
 def mfc_run(h, q, nsteps: int, cfl: float = 0.0, dt: float = 0.0, stream=None):
@@ -310,8 +313,8 @@ class Solver:
     def max_wavespeed(self, q):
         return mfc_max_wavespeed(self.h, q)
 
-    def step(self, q, cfl=0.0, dt=0.0):
-        mfc_rk3_step(self.h, q, cfl, dt)
+    def step(self, q, cfl=0.0, dt=0.0, dt_used=None):
+        mfc_rk3_step(self.h, q, cfl, dt, dt_used)
 
     def run(self, q, nsteps, cfl=0.0, dt=0.0):
         mfc_run(self.h, q, nsteps, cfl, dt)

@@ -77,7 +77,7 @@ def test_null_arguments(L):
         args = [None] * (len(f.argtypes))
         assert f(*args) == mfc.MFC_E_ARG, name
     assert L.mfc_rhs(None, None, None, None) == mfc.MFC_E_ARG
-    assert L.mfc_rk3_step(None, None, 0.3, 0.0, None) == mfc.MFC_E_ARG
+    assert L.mfc_rk3_step(None, None, 0.3, 0.0, None, None) == mfc.MFC_E_ARG
     assert L.mfc_free_grid(None) == mfc.MFC_OK
 
 
@@ -204,3 +204,4 @@ def test_batch_rejects_characteristic_faces(L):
     b = ctypes.c_void_p(123)
     assert L.mfc_batch_init(batch_descs(bc=(2, 2, 0, 0, 0, 0)), 3, ctypes.byref(b)) == mfc.MFC_E_ARG
     assert b.value is None
+
