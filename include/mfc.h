@@ -170,6 +170,24 @@ int mfc_fill_ghosts(mfc_grid *g, void *q, void *stream);
  * whatever the ghost cells of q hold. */
 int mfc_rhs(mfc_grid *g, const void *q, void *rhs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the right-hand
+ * side of mfc_rhs with MFC_KERNEL_SPLIT, from a descriptor and no grid handle.
+ * desc is validated as by mfc_init_grid and must describe a 3D grid of
+ * uniform cells with extrapolated or periodic faces and WENO5, WENO3 or
+ * first-order reconstruction (desc->kernel is ignored); q and rhs are device
+ * arrays of that grid's state layout in its precision, as for mfc_rhs (rhs
+ * ghost entries are not written; q's ghost cells are not read).  flag_dev is
+ * a caller-owned device int that the kernels set nonzero if a cell is
+ * non-physical; it is not cleared.  The one scratch buffer, the x+y part of
+ * every cell (nvar x padded cells x element size), lives in a 64 MiB device
+ * array that the library holds on every GPU it runs on until the process
+ * ends; grids needing more return MFC_E_ARG before anything is enqueued.
+ * Nothing is allocated.  Calls on the same GPU share that array: calls that
+ * overlap in time on one GPU (two streams, two host threads) race and give
+ * undefined results. */
+int mfc_rhs_noalloc(const mfc_grid_desc *desc, const void *q, void *rhs, int *flag_dev, void *stream);
+
 /* Largest signal speed max_cells max_d (|u_d| + c) over interior cells, the
  * quantity that bounds the explicit step through the CFL condition (Sec. 1;
  * c the frozen mixture sound speed of the stiffened-gas mixture, Sec. 2.1)

@@ -84,6 +84,12 @@ int launch_rhs_fused(mfc_grid *h, const void *q, const void *q0, void *out, int 
 int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
                      const double *dt_dev, hipStream_t s, double cfl = 0.0);
 
+// Split right-hand side (mode 0) without a handle: 3D uniform cells,
+// WENO5/WENO3/first order as g.order says, no learned routing and no
+// characteristic faces; lxy holds nvar arrays of the padded grid in the
+// storage type.
+int launch_rhs_split_raw(const Grid &g, bool fp32, const void *q, void *out, void *lxy, int *flag, hipStream_t s);
+
 // Split path: number of x+y workgroups of one launch (each writes one
 // wave-speed partial when the step size is computed inside the launch).
 int64_t split_xy_blocks(const Grid &g);

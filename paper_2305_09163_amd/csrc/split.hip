@@ -799,7 +799,41 @@ int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
     return hip_status(hipGetLastError(), "split right-hand side launch");
 }
 
+// The right-hand side (mode 0) on a grid with no handle: uniform cells,
+// extrapolated or periodic boundaries, WENO5, WENO3 or first order; the x+y
+// part goes to the caller's `lxy` (nvar arrays of the padded grid) and
+// non-physical cells set *flag.
+template <class T, int ORDER>
+int rhs_split_raw(const Grid &g, const T *q, T *out, T *lxy, int *flag, hipStream_t s)
+{
+    const dim3 gxy = xy_grid(g);
+    const dim3 gz((g.n[0] + kZX - 1) / kZX, (g.n[1] + kZY - 1) / kZY, (g.n[2] + kLZ<T> - 1) / kLZ<T>);
+    const T se = T(__builtin_sqrt(g.eps));
+    hipLaunchKernelGGL((k_xy<T, false, ORDER, false, false>), gxy, dim3(NT), 0, s, g, q, q, lxy, flag, nullptr, 0.f,
+                       se, nullptr, 0, 0, 0.0, nullptr);
+    hipLaunchKernelGGL((k_z<T, false, ORDER, false, false, false>), gz, dim3(kZX * kZY), 0, s, g, q, out, lxy, 0, 0.0,
+                       nullptr, flag, nullptr, 0.f, se);
+    return hip_status(hipGetLastError(), "split right-hand side launch");
+}
+
 }  // namespace
+
+int launch_rhs_split_raw(const Grid &g, bool fp32, const void *q, void *out, void *lxy, int *flag, hipStream_t s)
+{
+    if (g.ndim != 3 || g.stretched || g.cbc_mask) return fail(MFC_E_UNSUPPORTED, "3D uniform cells only");
+    if (fp32) {
+        const float *fq = (const float *)q;
+        float *fo = (float *)out, *fl = (float *)lxy;
+        if (g.order == 3) return rhs_split_raw<float, 3>(g, fq, fo, fl, flag, s);
+        if (g.order == 1) return rhs_split_raw<float, 1>(g, fq, fo, fl, flag, s);
+        return rhs_split_raw<float, 5>(g, fq, fo, fl, flag, s);
+    }
+    const double *dq = (const double *)q;
+    double *dout = (double *)out, *dl = (double *)lxy;
+    if (g.order == 3) return rhs_split_raw<double, 3>(g, dq, dout, dl, flag, s);
+    if (g.order == 1) return rhs_split_raw<double, 1>(g, dq, dout, dl, flag, s);
+    return rhs_split_raw<double, 5>(g, dq, dout, dl, flag, s);
+}
 
 int64_t split_xy_blocks(const Grid &g)
 {

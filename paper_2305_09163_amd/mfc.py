@@ -62,6 +62,7 @@ _SIGNATURES = {
     "mfc_cons_to_prim": [_VP, _VP, _VP, _VP],
     "mfc_fill_ghosts": [_VP, _VP, _VP],
     "mfc_rhs": [_VP, _VP, _VP, _VP],
+    "mfc_rhs_noalloc": [ctypes.POINTER(mfc_grid_desc), _VP, _VP, _VP, _VP],
     "mfc_max_wavespeed": [_VP, _VP, ctypes.POINTER(ctypes.c_double), _VP],
     "mfc_rk3_step": [_VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP],
     "mfc_run": [_VP, _VP, ctypes.c_int, ctypes.c_double, ctypes.c_double, _VP],
@@ -224,6 +225,14 @@ def mfc_rk3_step(h, q, cfl: float = 0.0, dt: float = 0.0, dt_used=None, stream=N
 
 def mfc_run(h, q, nsteps: int, cfl: float = 0.0, dt: float = 0.0, stream=None):
     _check(lib().mfc_run(h, _ptr(q), nsteps, cfl, dt, _stream(stream)), "mfc_run")
+
+
+def mfc_rhs_noalloc(desc, q, rhs, flag, stream=None):
+    """The right-hand side of mfc_rhs on the split kernels with no grid handle
+    and no device allocation; `flag` is a device int32 tensor that the
+    kernels set nonzero on a non-physical cell (the caller clears it)."""
+    _check(lib().mfc_rhs_noalloc(ctypes.byref(desc), _ptr(q), _ptr(rhs), _ptr(flag), _stream(stream)),
+           "mfc_rhs_noalloc")
 
 
 def mfc_time(h, stream=None):

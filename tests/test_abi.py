@@ -205,3 +205,34 @@ def test_batch_rejects_characteristic_faces(L):
     assert L.mfc_batch_init(batch_descs(bc=(2, 2, 0, 0, 0, 0)), 3, ctypes.byref(b)) == mfc.MFC_E_ARG
     assert b.value is None
 
+
+def test_noalloc_rhs_rejects_on_the_host(L):
+    """mfc_rhs_noalloc checks its arguments before any device call: null
+    pointers, descriptors mfc_init_grid would reject, configurations outside
+    the 3D split kernels, and grids whose x+y part exceeds its 64 MiB
+    scratch (nvar x padded cells x element size)."""
+    fake = ctypes.c_void_p(256)   # never dereferenced: every case fails first
+
+    def call(d, q=fake, r=ctypes.c_void_p(512), f=ctypes.c_void_p(768)):
+        return L.mfc_rhs_noalloc(ctypes.byref(d) if d is not None else None, q, r, f, None)
+
+    def d3(n, **kw):
+        d = mfc.make_desc(W.GridSpec(ndim=3, n=n), kernel=mfc.MFC_KERNEL_SPLIT)
+        for k, v in kw.items():
+            setattr(d, k, v)
+        return d
+
+    assert call(None) == mfc.MFC_E_ARG
+    assert call(d3((8, 8, 8)), q=None) == mfc.MFC_E_ARG
+    assert call(d3((8, 8, 8)), f=None) == mfc.MFC_E_ARG
+    assert call(d3((8, 8, 8)), q=fake, r=fake) == mfc.MFC_E_ARG            # q and rhs alias
+    assert call(desc(n=(2, 8, 8))) == mfc.MFC_E_ARG                         # what mfc_init_grid rejects
+    d2 = mfc.make_desc(W.GridSpec(ndim=2, n=(16, 16)), kernel=mfc.MFC_KERNEL_FUSED)
+    assert call(d2) == mfc.MFC_E_UNSUPPORTED                                # split kernels are 3D
+    assert call(d3((8, 8, 8), recon=mfc.MFC_RECON_LEARNED)) == mfc.MFC_E_UNSUPPORTED
+    dc = d3((8, 8, 8))
+    dc.bc[0] = dc.bc[1] = mfc.MFC_BC_CHARACTERISTIC
+    assert call(dc) == mfc.MFC_E_UNSUPPORTED
+    # 7 x 107^3 x 8 B = 68.6 MB > 64 MiB in FP64; the same grid fits in FP32
+    assert call(d3((101, 101, 101))) == mfc.MFC_E_ARG
+    assert b"64 MiB" in L.mfc_last_error_detail()
