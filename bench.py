@@ -46,28 +46,34 @@ FLOPS_PER_CELL_UPDATE_2D = 1561
 # result (56 B): (112 + 168 + 168) / 3.
 BYTES_PER_CELL_UPDATE = (112 + 168 + 168) / 3
 # The split path's two kernels.  x+y kernel: conservative->primitive 28 and
-# two directions of 870 -> 1769 flops; reads the stage input (56 B) and
-# writes the x+y part (8 values, 64 B).  z kernel: the remaining
+# two directions of 870 -> 1769 flops; reads the stage input (56 B) and, on
+# stages 2-3 where it forms the x+y part of the stage combination, q^n
+# (56 B), and writes that x+y part (7 values, 56 B): (112 + 168 + 168) / 3 B
+# averaged over a step's three stages.  z kernel: the remaining
 # 2669 - 1769 = 900 flops (one direction, the source, the stage update);
-# reads the stage input, the x+y part and q^n on stages 2-3, writes the
-# result: 56 + 64 + 56 * 2/3 + 56 B.
-SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences)", flops=1769, bytes=56 + 64),
+# reads the stage input and the x+y part, writes the result: 3 x 56 B (the
+# first stage of a CFL step reads its stage input a second time, which the
+# algorithmic count leaves out).
+SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences, x+y stage combination)", flops=1769,
+                 bytes=(112 + 168 + 168) / 3),
          1: dict(name="k_z (z reconstruction, HLLC, source, stage update)", flops=2669 - 1769,
-                 bytes=56 + 64 + 56 * 2 / 3 + 56)}
+                 bytes=3 * 56)}
 # The library's kernel events bracket the launches of every tenth step of
 # the timed region.
 KERNEL_TIMING_STRIDE = 10
 # Measured HBM traffic per launch (bytes) of the split path's kernels on the
 # 128^3 bubble: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each
 # scaled by its reading for a copy kernel of known size (FETCH_SIZE x 2.00,
-# WRITE_SIZE x 1.00).  Valid only for the kernel sources they were taken on;
-# any change to those files turns `traffic` back to null.
-TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h")
-TRAFFIC = {"sha256": "1ac26a4a42dcee10382dbf918403f58b981e7baef2f2068a3ba3e6175b9fc1dc",
-           ("split", "fp32", 128, 0): (61.76e6, 70.32e6),
-           ("split", "fp32", 128, 1): (246.29e6, 62.41e6),
-           ("split", "fp64", 128, 0): (124.82e6, 139.49e6),
-           ("split", "fp64", 128, 1): (515.55e6, 124.15e6)}
+# WRITE_SIZE x 1.00), averaged over the three stages of a step (the z
+# kernel's first stage reads its stage input twice).  Valid only for the
+# kernel sources they were taken on; any change to those files turns
+# `traffic` back to null.
+TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h", "charbc.h")
+TRAFFIC = {"sha256": "33cd438c4431b6ebc3304b7d41bc4f09b4c58d919db5e1f99ba2ad6ce30e6183",
+           ("split", "fp32", 128, 0): (124.71e6, 62.42e6),
+           ("split", "fp32", 128, 1): (159.18e6, 61.58e6),
+           ("split", "fp64", 128, 0): (238.28e6, 127.50e6),
+           ("split", "fp64", 128, 1): (329.31e6, 123.85e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12

@@ -168,6 +168,20 @@ __device__ __forceinline__ bool plane_char_rate(const Grid &g, const T (&pl)[7][
     return char_rate<3, D, SIDE, T>(g, W[0], W[1], W[2], inv_dx, rate);
 }
 
+// A load of data the x+y pass reads once (q^n for its part of the stage
+// combination), marked non-temporal so that it does not evict the halo
+// cells that neighbouring tiles read from L2 (FP64: 1.2 % faster measured;
+// MFC_XY_NT=0 turns it off).
+#ifndef MFC_XY_NT
+#define MFC_XY_NT 1
+#endif
+template <class T>
+__device__ __forceinline__ T ld_once(const T *p)
+{
+    if constexpr (MFC_XY_NT != 0) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // Load and convert cell (i, j, bc_cell(k)) of a column (i, j interior).
 template <class T>
 __device__ __forceinline__ void load_cons_z(const Grid &g, const T *__restrict__ q, int i, int j, int k, T *qc)
@@ -215,7 +229,7 @@ constexpr int kXYWaves = ROUTE ? 2 : (STRETCH ? (sizeof(T) == 8 ? 2 : 4) : (size
 // the plane's work, measured faster), or loads them at its end (FP32, whose
 // five wavefronts per SIMD leave no registers for them).
 #ifndef MFC_XY_HOLD64
-#define MFC_XY_HOLD64 0
+#define MFC_XY_HOLD64 1
 #endif
 template <class T>
 constexpr bool kHoldFold = sizeof(T) == 8 ? MFC_XY_HOLD64 : 0;
@@ -355,7 +369,7 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
             if (mode != 1) {
                 const int64_t c = offset(g, gx, gy, k);
 #pragma unroll
-                for (int v = 0; v < NV; v++) q0c[v] = q0[v * g.vstride + c];
+                for (int v = 0; v < NV; v++) q0c[v] = ld_once(&q0[v * g.vstride + c]);
             }
         }
         if (k + 1 < z1) fetch(k + 1);
@@ -560,7 +574,7 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
 #endif
 // odd z chunks marched downward (see k_z)
 #ifndef MFC_Z_ALT
-#define MFC_Z_ALT 0
+#define MFC_Z_ALT 1
 #endif
 
 template <class T>
