@@ -123,6 +123,7 @@ def _load(path):
         "ora_sound_speed2": (ctypes.c_double, [G, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
         "ora_kapila_K": (ctypes.c_double, [G, _D]),
         "ora_cbc_cell": (None, [G, ctypes.c_int, ctypes.c_int, _D, _D, _D]),
+        "ora_one_sided_coef": (None, [G, ctypes.c_int, ctypes.c_int, _D]),
         "ora_prim_to_cons": (None, [G, _D, _D]),
         "ora_cons_to_prim": (ctypes.c_int, [G, _D, _D]),
         "ora_weno5": (None, [_D, ctypes.c_double, _D, _D, _D]),
@@ -289,6 +290,15 @@ def cbc_cell(spec, d: int, side: int, w_cell, dwdx):
     w, dw = _arr(w_cell), _arr(dwdx)
     out = np.empty(spec.nvar)
     lib().ora_cbc_cell(ctypes.byref(grid(spec)), d, side, _ptr(w), _ptr(dw), _ptr(out))
+    return out
+
+
+def one_sided_coef(spec, d: int, side: int):
+    """Coefficients of the second-order one-sided derivative along d at the
+    centre of the boundary cell of face `side` (0 low, 1 high), for the
+    values of that cell and the next two cells into the domain."""
+    out = np.empty(3)
+    lib().ora_one_sided_coef(ctypes.byref(grid(spec)), d, side, _ptr(out))
     return out
 
 

@@ -643,6 +643,27 @@ void ora_cbc_cell(const ora_grid *g, int d, int side, const double *w, const dou
     dqdt[nv - 1] = at;
 }
 
+/* Coefficients c[0..2] of the second-order one-sided derivative along d at
+ * the centre of the boundary cell of face `side` (0 low, 1 high), applied to
+ * the values of that cell and of the next two cells into the domain: the
+ * derivative at x0 of the quadratic through (x_t, f_t), t = 0, 1, 2, where
+ * x_t are the centres of cells b, b + s, b + 2s (b = 0, s = +1 on the low
+ * face; b = n - 1, s = -1 on the high face).  On the non-uniform cells of
+ * the structured mesh (Sec. 4.1) the centres come from the face
+ * coordinates; on uniform cells this is s (-3, 4, -1) / (2 dx). */
+void ora_one_sided_coef(const ora_grid *g, int d, int side, double c[3])
+{
+    int n = g->n[d], s = side == 0 ? 1 : -1, b = side == 0 ? 0 : n - 1;
+    double x[3];
+    for (int t = 0; t < 3; t++) {
+        int i = b + s * t;
+        x[t] = g->faces[d] ? 0.5 * (g->faces[d][i] + g->faces[d][i + 1]) : (i + 0.5) * g->dx[d];
+    }
+    c[0] = 1.0 / (x[0] - x[1]) + 1.0 / (x[0] - x[2]);
+    c[1] = (x[0] - x[2]) / ((x[1] - x[0]) * (x[1] - x[2]));
+    c[2] = (x[0] - x[1]) / ((x[2] - x[0]) * (x[2] - x[1]));
+}
+
 /* ---------------------------------------------------------------------- */
 /* Right-hand side (Sec. 3.1, eq. fvmdis)                                   */
 /* ---------------------------------------------------------------------- */
@@ -784,9 +805,12 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                     int side = cell == 0 && g->bc[2 * d] == 2 ? 0 : (cell == n - 1 && g->bc[2 * d + 1] == 2 ? 1 : -1);
                     if (side >= 0) {
                         /* characteristic boundary cell: second-order one-sided
-                         * derivative of the primitives into the domain */
-                        double wc[MAXV], dw[MAXV], dq[MAXV];
+                         * derivative of the primitives into the domain (on
+                         * non-uniform cells, that of the quadratic through
+                         * the three cell centres) */
+                        double wc[MAXV], dw[MAXV], dq[MAXV], cs[3];
                         int sg = side == 0 ? 1 : -1;
+                        if (g->faces[d]) ora_one_sided_coef(g, d, side, cs);
                         for (int v = 0; v < nv; v++) {
                             double f[3];
                             for (int t = 0; t < 3; t++) {
@@ -794,7 +818,10 @@ int ora_rhs(const ora_grid *g, const double *q, double *rhs)
                                 f[t] = w[at(g, v, c[0], c[1], c[2])];
                             }
                             wc[v] = f[0];
-                            dw[v] = sg * (-3.0 * f[0] + 4.0 * f[1] - f[2]) * 0.5 * inv_dx;
+                            if (g->faces[d])
+                                dw[v] = cs[0] * f[0] + cs[1] * f[1] + cs[2] * f[2];
+                            else
+                                dw[v] = sg * (-3.0 * f[0] + 4.0 * f[1] - f[2]) * 0.5 * inv_dx;
                         }
                         c[d] = cell;
                         ora_cbc_cell(g, d, side, wc, dw, dq);

@@ -130,36 +130,77 @@ def test_acoustic_pulse_leaves_without_reflection():
     assert np.abs(resid).max() < 0.1 * np.abs(resid_ex).max()
 
 
-def test_boundary_cell_rate_converges_at_second_order():
+def boundary_rate_error(n, stretched=False):
     """Smooth supersonic outflow through the high end (every wave leaves):
-    the boundary cell's right-hand side tends to the exact rate of the
-    primitive system at the cell centre at second order (the one-sided
-    derivatives), checked between 50, 100 and 200 cells."""
-    def err(n):
-        spec = W.GridSpec(ndim=1, n=(n,), bc=(0, 2, 0, 0, 0, 0))
-        x = spec.centres(0)
-        k = 2 * np.pi
-        a1 = 0.5 + 0.2 * np.sin(k * x)
-        p = 1e5 * (1 + 0.05 * np.cos(k * x))
-        r1, r2 = 1000.0 * (1 + 0.01 * np.sin(k * x)), 2.0 * (1 + 0.05 * np.cos(k * x))
-        u = 3000.0 + 50.0 * np.sin(k * x)          # supersonic in the mixture near x = 1
-        w = np.zeros(spec.shape)
-        w[0], w[1], w[2], w[3], w[4] = a1 * r1, (1 - a1) * r2, u, p, a1
-        q = oracle.fill_ghosts(spec, oracle.prim_to_cons_field(spec, w))
-        L, st = oracle.rhs(spec, q)
-        assert st == oracle.OK
-        xb = x[3 + n - 1]
-        # exact values and derivatives at the boundary cell centre
-        f = lambda t: np.array([(0.5 + 0.2 * np.sin(k * t)) * 1000.0 * (1 + 0.01 * np.sin(k * t)),  # noqa: E731
-                                (0.5 - 0.2 * np.sin(k * t)) * 2.0 * (1 + 0.05 * np.cos(k * t)),
-                                3000.0 + 50.0 * np.sin(k * t), 1e5 * (1 + 0.05 * np.cos(k * t)),
-                                0.5 + 0.2 * np.sin(k * t)])
-        h = 1e-6
-        wb, dwb = f(xb), (f(xb + h) - f(xb - h)) / (2 * h)
-        c = np.sqrt(oracle.sound_speed2(spec, wb[0] + wb[1], wb[3], wb[4]))
-        assert wb[2] > c
-        want = conservative_rate(spec, wb, primitive_rates(spec, wb, dwb, 0))
-        got = L[:, 0, 0, 3 + n - 1]
-        return np.abs(got - want).max() / np.abs(want).max()
-    e = [err(n) for n in (50, 100, 200)]
+    relative error of the boundary cell's right-hand side against the exact
+    rate of the primitive system at the cell centre.  stretched: tanh cells
+    refined towards the boundary (Sec. 4.1's structured non-uniform mesh)."""
+    faces = (W.tanh_faces(n, centre=0.9, depth=0.6), None, None) if stretched else None
+    spec = W.GridSpec(ndim=1, n=(n,), bc=(0, 2, 0, 0, 0, 0), faces=faces)
+    x = spec.centres(0)
+    k = 2 * np.pi
+    f = lambda t: np.array([(0.5 + 0.2 * np.sin(k * t)) * 1000.0 * (1 + 0.01 * np.sin(k * t)),  # noqa: E731
+                            (0.5 - 0.2 * np.sin(k * t)) * 2.0 * (1 + 0.05 * np.cos(k * t)),
+                            3000.0 + 50.0 * np.sin(k * t), 1e5 * (1 + 0.05 * np.cos(k * t)),
+                            0.5 + 0.2 * np.sin(k * t)])
+    w = np.zeros(spec.shape)
+    w[:, 0, 0, :] = f(x)                           # u supersonic in the mixture near x = 1
+    q = oracle.fill_ghosts(spec, oracle.prim_to_cons_field(spec, w))
+    L, st = oracle.rhs(spec, q)
+    assert st == oracle.OK
+    xb = x[3 + n - 1]
+    h = 1e-6
+    wb, dwb = f(xb), (f(xb + h) - f(xb - h)) / (2 * h)
+    c = np.sqrt(oracle.sound_speed2(spec, wb[0] + wb[1], wb[3], wb[4]))
+    assert wb[2] > c
+    want = conservative_rate(spec, wb, primitive_rates(spec, wb, dwb, 0))
+    got = L[:, 0, 0, 3 + n - 1]
+    return np.abs(got - want).max() / np.abs(want).max()
+
+
+def test_boundary_cell_rate_converges_at_second_order():
+    """The one-sided derivatives make the boundary cell's rate second-order
+    accurate, checked between 50, 100 and 200 cells."""
+    e = [boundary_rate_error(n) for n in (50, 100, 200)]
     assert np.log2(e[0] / e[1]) >= 1.9 and np.log2(e[1] / e[2]) >= 1.9, e
+
+
+def test_boundary_cell_rate_converges_at_second_order_on_stretched_cells():
+    """As above on tanh-stretched cells, whose one-sided derivative is that of
+    the quadratic through the three cell centres (the uniform stencil with
+    the boundary cell's width is only first-order accurate there)."""
+    e = [boundary_rate_error(n, stretched=True) for n in (100, 200, 400)]
+    assert np.log2(e[0] / e[1]) >= 1.85 and np.log2(e[1] / e[2]) >= 1.9, e
+
+
+def random_faces(rng, n):
+    w = rng.uniform(0.3, 3.0, size=n)
+    return np.concatenate([[0.0], np.cumsum(w)]) / w.sum()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_one_sided_coefficients_are_exact_for_quadratics(seed):
+    """On random non-uniform cells the one-sided derivative at the boundary
+    cell's centre is exact for any quadratic, at both ends."""
+    rng = np.random.default_rng(W.SEED + 90 + seed)
+    n = int(rng.integers(3, 10))
+    fc = random_faces(rng, n)
+    spec = W.GridSpec(ndim=1, n=(n,), bc=(2, 2, 0, 0, 0, 0), faces=(fc, None, None))
+    x = 0.5 * (fc[1:] + fc[:-1])
+    a, b, c = rng.normal(size=3)
+    val = a + b * x + c * x ** 2
+    for side, idx in ((0, [0, 1, 2]), (1, [n - 1, n - 2, n - 3])):
+        cf = oracle.one_sided_coef(spec, 0, side)
+        want = b + 2 * c * x[idx[0]]
+        assert abs(cf @ val[idx] - want) <= 1e-12 * n * (abs(a) + abs(b) + abs(c)), (side, cf)
+        assert abs(cf.sum()) <= 1e-12 * n * np.abs(cf).max()
+
+
+def test_one_sided_coefficients_on_uniform_cells():
+    """Uniform cells (by spacing or by face list) give s (-3, 4, -1)/(2 dx)."""
+    for n in (3, 7, 20):
+        for faces in (None, (np.linspace(0.0, 1.0, n + 1), None, None)):
+            spec = W.GridSpec(ndim=1, n=(n,), bc=(2, 2, 0, 0, 0, 0), faces=faces)
+            for side, s in ((0, 1.0), (1, -1.0)):
+                cf = oracle.one_sided_coef(spec, 0, side)
+                np.testing.assert_allclose(cf, s * np.array([-1.5, 2.0, -0.5]) * n, rtol=1e-12)

@@ -51,6 +51,11 @@ MUTANTS = {
     "cbc velocity rate factor": ("-(L5 - L1) / (2.0 * rho * c)", "-(L5 - L1) / (rho * c)"),
     "cbc partial density coupling": ("rkt[k] = -Lk[k] - w[k] / (rho * c2) * 0.5 * (L5 + L1);", "rkt[k] = -Lk[k];"),
     "cbc one-sided stencil": ("sg * (-3.0 * f[0] + 4.0 * f[1] - f[2]) * 0.5 * inv_dx", "sg * (-f[0] + f[1]) * inv_dx"),
+    "cbc uniform stencil on non-uniform cells": ("dw[v] = cs[0] * f[0] + cs[1] * f[1] + cs[2] * f[2];",
+                                                 "dw[v] = sg * (-3.0 * f[0] + 4.0 * f[1] - f[2]) * 0.5 * inv_dx;"),
+    "cbc non-uniform points at faces": ("x[t] = g->faces[d] ? 0.5 * (g->faces[d][i] + g->faces[d][i + 1])",
+                                        "x[t] = g->faces[d] ? g->faces[d][i]"),
+    "cbc one-sided middle coefficient sign": ("c[1] = (x[0] - x[2]) /", "c[1] = (x[2] - x[0]) /"),
     "cbc energy volume-fraction term": ("((G1 - G0) * p + (P1 - P0)) * at", "((G1 - G0) * p) * at"),
     "non-uniform cfl width": ("double r = ora_cell_width(g, d, idx[d]) / (fabs(wc[2 + d]) + c);", "double r = ora_cell_width(g, d, 0) / (fabs(wc[2 + d]) + c);"),
     "rhs flux difference sign": ("(Ff[cell * nv + v] - Ff[(cell + 1) * nv + v]) * inv_dx", "(Ff[(cell + 1) * nv + v] - Ff[cell * nv + v]) * inv_dx"),
