@@ -64,8 +64,10 @@ enum {
  * and on each boundary cell the finite-volume terms normal to the face are
  * replaced by the characteristic form of the one-dimensional system, with
  * wave amplitudes from second-order one-sided differences of the primitives
- * and every amplitude whose wave enters the domain set to zero (Allaire
- * model, uniform cells; not in batches). */
+ * (on non-uniform cells, the derivative of the quadratic through the
+ * boundary cell's centre and the next two) and every amplitude whose wave
+ * enters the domain set to zero (Allaire model; with the learned routing on
+ * the split kernel only; not in batches). */
 enum { MFC_BC_EXTRAP = 0, MFC_BC_PERIODIC = 1, MFC_BC_CHARACTERISTIC = 2 };
 enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
 /* Reconstruction of the primitive variables at the faces (Sec. 3.2):
@@ -119,7 +121,8 @@ typedef struct {
                             n_d + 1 strictly increasing interior face coordinates
                             along d, copied at mfc_init_grid (lo/hi of that
                             dimension are then ignored); NULL for uniform cells.
-                            Supported by MFC_KERNEL_FUSED with MFC_RECON_WENO5
+                            Supported by MFC_KERNEL_FUSED and (3D)
+                            MFC_KERNEL_SPLIT with MFC_RECON_WENO5
                             (WENO5 with per-cell coefficients from the widths)
                             or MFC_RECON_FIRST_ORDER; ghost cells take the widths
                             of the cells the ghost fill copies into them.

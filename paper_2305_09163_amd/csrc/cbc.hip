@@ -68,7 +68,7 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
     constexpr int sg = SIDE == 0 ? 1 : -1;
     const int n = g.n[D];
     const int b = SIDE == 0 ? 0 : n - 1;
-    const T idx = T(g.inv_dx[D]);
+    const T idx = T(inv_width(g, D, b));   // 1/dx_D, or 1/width of the boundary cell on non-uniform cells
     bool bad = false;
 
     T W[4][NV];
@@ -98,15 +98,18 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
     // at b-1/2 (left state: cell b-1 reconstructed from stencil cells 0..4,
     // right state: cell b from 1..5), lane 1 the flux at b+1/2 (cells b from
     // 1..5 and b+1 from 2..6), and exchange them.
+    // On non-uniform cells the two cells of the face reconstruct with their
+    // own WENO5 coefficients (cells b - 1 + half and b + half).
     constexpr int i0 = at<SIDE>(0), i1 = at<SIDE>(1), i2 = at<SIDE>(2), i3 = at<SIDE>(3), i4 = at<SIDE>(4),
                   i5 = at<SIDE>(5), i6 = at<SIDE>(6);
+    const double *cl = coef_row(g, D, b - 1 + half), *cr = coef_row(g, D, b + half);
     T lft[NV], rgt[NV], dummy;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
         const T s0 = half ? W[i1][v] : W[i0][v], s1 = half ? W[i2][v] : W[i1][v], s2 = half ? W[i3][v] : W[i2][v],
                 s3 = half ? W[i4][v] : W[i3][v], s4 = half ? W[i5][v] : W[i4][v], s5 = half ? W[i6][v] : W[i5][v];
-        recon_pair<ORDER, T>(s0, s1, s2, s3, s4, T(g.eps), lft[v], dummy);
-        recon_pair<ORDER, T>(s1, s2, s3, s4, s5, T(g.eps), dummy, rgt[v]);
+        recon_cell<ORDER, T>(cl, s0, s1, s2, s3, s4, T(g.eps), lft[v], dummy);
+        recon_cell<ORDER, T>(cr, s1, s2, s3, s4, s5, T(g.eps), dummy, rgt[v]);
     }
     T F[NV], uf;
     bad |= hllc<NDIM, D, T>(g, lft, rgt, F, uf);
@@ -121,7 +124,7 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
 
     // characteristic form on the boundary cell
     T rate[NV];
-    bad |= char_rate<NDIM, D, SIDE, T>(g, W[0], W[1], W[2], idx, rate);
+    bad |= char_rate<NDIM, D, SIDE, T>(g, W[0], W[1], W[2], idx, one_sided<T>(g, D, SIDE), rate);
 #pragma unroll
     for (int v = 0; v < NV; v++) delta[v] += rate[v] - fv[v];
     return bad;

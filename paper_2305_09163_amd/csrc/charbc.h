@@ -8,10 +8,28 @@
 
 namespace mfc {
 
+// Weights of the one-sided derivative at the boundary cell of a
+// characteristic face on a non-uniform dimension (Grid::cbc_cf), in the
+// arithmetic's type; `on` is false on a uniform dimension.
+template <class T>
+struct OneSided {
+    T c[3];
+    bool on;
+};
+template <class T>
+__device__ __forceinline__ OneSided<T> one_sided(const Grid &g, int d, int side)
+{
+    OneSided<T> o;
+    o.on = g.wcoef[d] != nullptr;
+#pragma unroll
+    for (int t = 0; t < 3; t++) o.c[t] = T(g.cbc_cf[2 * d + side][t]);
+    return o;
+}
+
 // Rates of the conservative rows of a boundary cell on the characteristic
 // face SIDE (0: low, 1: high) normal to dimension D, from the primitives of
 // the boundary cell W0 and of the next two cells into the domain W1, W2
-// (idx = 1/dx_D).  Wave amplitudes L1 = (u-c)(p_x - rho c u_x),
+// (uniform cells: idx = 1/dx_D; non-uniform: the weights os).  Wave amplitudes L1 = (u-c)(p_x - rho c u_x),
 // L5 = (u+c)(p_x + rho c u_x), L_k = u((alpha_k rho_k)_x - alpha_k rho_k
 // p_x/(rho c^2)), L_t = u (u_t)_x, L_a = u (alpha1)_x from second-order
 // one-sided differences into the domain, every amplitude whose wave enters
@@ -20,7 +38,8 @@ namespace mfc {
 // (u_t)_t = -L_t, (alpha1)_t = -L_a, carried to the conservative rows
 // through the mixture EOS.  Returns true if the cell is non-physical.
 template <int NDIM, int D, int SIDE, class T>
-__device__ __forceinline__ bool char_rate(const Grid &g, const T *W0, const T *W1, const T *W2, T idx, T *rate)
+__device__ __forceinline__ bool char_rate(const Grid &g, const T *W0, const T *W1, const T *W2, T idx,
+                                          const OneSided<T> &os, T *rate)
 {
     constexpr int NV = 4 + NDIM, A = 3 + NDIM, E = 2 + NDIM;
     constexpr int sg = SIDE == 0 ? 1 : -1;
@@ -28,7 +47,9 @@ __device__ __forceinline__ bool char_rate(const Grid &g, const T *W0, const T *W
     const T *wb = W0;
     T dw[NV];
 #pragma unroll
-    for (int v = 0; v < NV; v++) dw[v] = T(sg) * (T(-3) * wb[v] + T(4) * W1[v] - W2[v]) * (T(0.5) * idx);
+    for (int v = 0; v < NV; v++)
+        dw[v] = os.on ? fmaT(os.c[2], W2[v], fmaT(os.c[1], W1[v], os.c[0] * wb[v]))
+                      : T(sg) * (T(-3) * wb[v] + T(4) * W1[v] - W2[v]) * (T(0.5) * idx);
     T Gam, Pi;
     mixture<T>(g, wb[A], Gam, Pi);
     const T rho = wb[0] + wb[1], p = wb[E], un = wb[2 + D];

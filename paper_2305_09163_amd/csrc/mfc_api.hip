@@ -89,6 +89,25 @@ void make_grid(const mfc_grid_desc &desc, Grid &g)
     g.stretched = 0;
     for (int d = 0; d < desc.ndim; d++) g.stretched |= desc.faces[d] != nullptr;
     if (g.stretched) g.dxmin = 1.0;   // the reduction then returns max (|u_d| + c)/dx_d
+    // one-sided derivative at the boundary cell of a non-uniform dimension
+    // (characteristic faces, Sec. 3.3): that of the quadratic through the
+    // centres x0 (the boundary cell), x1, x2 (the next two into the domain);
+    // with h1 = x1 - x0, h2 = x2 - x0 the weights of f1 and f2 are
+    // h2 / (h1 (h2 - h1)) and -h1 / (h2 (h2 - h1)), and f0 takes minus
+    // their sum (constants have no derivative)
+    for (int d = 0; d < desc.ndim; d++) {
+        const double *f = desc.faces[d];
+        if (!f) continue;
+        for (int side = 0; side < 2; side++) {
+            const int n = desc.n[d], b = side ? n - 1 : 0, s = side ? -1 : 1;
+            auto centre = [&](int i) { return 0.5 * (f[i] + f[i + 1]); };
+            const double h1 = centre(b + s) - centre(b), h2 = centre(b + 2 * s) - centre(b);
+            double *c = g.cbc_cf[2 * d + side];
+            c[1] = h2 / (h1 * (h2 - h1));
+            c[2] = -h1 / (h2 * (h2 - h1));
+            c[0] = -(c[1] + c[2]);
+        }
+    }
 }
 
 namespace {
@@ -292,10 +311,10 @@ int validate(const mfc_grid_desc *d)
         if (a == MFC_BC_CHARACTERISTIC || b == MFC_BC_CHARACTERISTIC) {
             if (d->model != MFC_MODEL_ALLAIRE)
                 return fail(MFC_E_UNSUPPORTED, "characteristic boundaries take the Allaire model");
-            for (int e = 0; e < d->ndim; e++)
-                if (d->faces[e]) return fail(MFC_E_UNSUPPORTED, "characteristic boundaries need uniform cells");
-            if (d->recon == MFC_RECON_LEARNED)
-                return fail(MFC_E_UNSUPPORTED, "characteristic boundaries with the learned routing");
+            // the boundary pass of the other kernels recomputes the normal
+            // terms with WENO5, the split kernels keep their own (routed) ones
+            if (d->recon == MFC_RECON_LEARNED && d->kernel != MFC_KERNEL_SPLIT)
+                return fail(MFC_E_UNSUPPORTED, "characteristic boundaries with the learned routing need the split kernel");
         }
         if ((a == MFC_BC_PERIODIC) != (b == MFC_BC_PERIODIC))
             return fail(MFC_E_ARG, "periodic must be set on both faces of a dimension");

@@ -55,6 +55,10 @@ struct Grid {
     int cbc_mask;
     void *cbc_fv;
     int64_t cbc_off[6];
+    // characteristic face f on a non-uniform dimension: weights of the
+    // boundary cell and of the next two cells into the domain in the
+    // second-order one-sided derivative at the boundary cell's centre
+    double cbc_cf[6][3];
 };
 constexpr int kStretchCoef = 42;
 

@@ -165,7 +165,7 @@ __device__ __forceinline__ bool plane_char_rate(const Grid &g, const T (&pl)[7][
     for (int j = 0; j < 3; j++)
 #pragma unroll
         for (int v = 0; v < 7; v++) W[j][v] = D == 0 ? pl[v][r][c + sg * j] : pl[v][r + sg * j][c];
-    return char_rate<3, D, SIDE, T>(g, W[0], W[1], W[2], inv_dx, rate);
+    return char_rate<3, D, SIDE, T>(g, W[0], W[1], W[2], inv_dx, one_sided<T>(g, D, SIDE), rate);
 }
 
 // A load of data the x+y pass reads once (q^n for its part of the stage
@@ -526,8 +526,15 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
                 for (int v = 0; v < NV; v++) lxy[v * g.vstride + c] = L[v];
             }
         }
-        // the next plane overwrites s_plane (last read before the y-face
-        // barrier), s_minus and s_flux only after one and two more barriers
+        // The next plane overwrites s_plane, s_minus and s_flux only after
+        // zero, one and two more barriers.  s_plane is last read before the
+        // y-face barrier, except by the characteristic rate of a y face's
+        // boundary cells above, which reads the next two rows (other
+        // threads' slots): a workgroup whose tile has such cells waits here
+        // (the condition is the same for all its threads).
+        if (KEEP && (g.cbc_mask & 12) &&
+            (((g.cbc_mask & 4) && y0 == 0) || ((g.cbc_mask & 8) && y0 + TY >= g.n[1])))
+            __syncthreads();
     }
     if (smax_partial) {
         // workgroup maximum: wavefront butterflies, then one value per wavefront
@@ -866,6 +873,13 @@ int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int 
     float *fo = (float *)out;
     double *dout = (double *)out;
     const bool f32 = h->desc.precision == MFC_FP32_MIXED;
+    if (h->g.stretched && h->g.cbc_mask) {   // non-uniform cells with characteristic faces
+        if (h->desc.recon == MFC_RECON_FIRST_ORDER)
+            return f32 ? rhs_split<float, false, 1, true, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                       : rhs_split<double, false, 1, true, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+        return f32 ? rhs_split<float, false, 5, true, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                   : rhs_split<double, false, 5, true, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+    }
     if (h->g.stretched) {   // non-uniform cells: WENO5 or first order (checked at init)
         if (h->desc.recon == MFC_RECON_FIRST_ORDER)
             return f32 ? rhs_split<float, false, 1, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
@@ -873,7 +887,10 @@ int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int 
         return f32 ? rhs_split<float, false, 5, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
                    : rhs_split<double, false, 5, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
     }
-    if (h->g.cbc_mask) {   // characteristic faces (WENO5, WENO3 or first order; checked at init)
+    if (h->g.cbc_mask) {   // characteristic faces (WENO5, WENO3, first order or routed; checked at init)
+        if (learned)
+            return f32 ? rhs_split<float, true, 5, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
+                       : rhs_split<double, true, 5, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
         if (h->desc.recon == MFC_RECON_WENO3)
             return f32 ? rhs_split<float, false, 3, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
                        : rhs_split<double, false, 3, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);

@@ -190,14 +190,22 @@ def test_init_rejects_unsupported_characteristic_faces(L, kw, code):
     assert h.value is None
 
 
-def test_characteristic_faces_need_uniform_cells(L):
+def test_characteristic_faces_on_non_uniform_cells(L):
+    """Characteristic faces combine with non-uniform cells on the fused and
+    split kernels (validation passes: without a device the call fails later,
+    at the device query), not on the staged kernel."""
     import dataclasses
     spec, _ = W.bubble_collapse_3d(n=(8, 8, 8))
     spec = dataclasses.replace(spec, faces=(None, W.tanh_faces(8, depth=0.5), None), bc=(2, 2, 0, 0, 0, 0))
-    d = mfc.make_desc(spec, kernel=mfc.MFC_KERNEL_FUSED)
-    h = ctypes.c_void_p(123)
-    assert L.mfc_init_grid(ctypes.byref(d), ctypes.byref(h)) == mfc.MFC_E_UNSUPPORTED
-    assert h.value is None
+    for kernel, ok in ((mfc.MFC_KERNEL_FUSED, True), (mfc.MFC_KERNEL_SPLIT, True), (mfc.MFC_KERNEL_STAGED, False)):
+        d = mfc.make_desc(spec, kernel=kernel)
+        h = ctypes.c_void_p(123)
+        st = L.mfc_init_grid(ctypes.byref(d), ctypes.byref(h))
+        assert (st != mfc.MFC_E_UNSUPPORTED) if ok else (st == mfc.MFC_E_UNSUPPORTED), (kernel, st)
+        if st != mfc.MFC_OK:
+            assert h.value is None
+        else:
+            L.mfc_free_grid(h)
 
 
 def test_batch_rejects_characteristic_faces(L):

@@ -147,6 +147,67 @@ def test_cbc_other_orders(name, kernel, recon):
     assert err.max() <= 1e-12 and (e1 <= bar).all(), (e1, bar)
 
 
+def with_faces(sw, faces):
+    spec, w = sw
+    return dataclasses.replace(spec, faces=faces), w
+
+
+# characteristic faces on the non-uniform cells of Sec. 4.1 (tanh-stretched)
+STRETCHED = {
+    "smooth_1d_tanh": lambda: with_bc(with_faces(W.random_smooth_periodic(1, 40),
+                                                 (W.tanh_faces(40, centre=0.1, depth=0.5), None, None)), ALL),
+    "smooth_2d_tanh_x": lambda: with_bc(with_faces(W.random_smooth_periodic(2, 21),
+                                                   (W.tanh_faces(21, centre=0.8, depth=0.5), None, None)), ALL),
+    "bubble_3d_tanh": lambda: with_bc(W.bubble_collapse_3d(n=(17, 15, 17), stretch=0.6), ALL),
+    "smooth_3d_mixed_tanh_z": lambda: with_bc(with_faces(W.random_smooth_periodic(3, 17),
+                                                         (None, None, W.tanh_faces(17, centre=0.2, depth=0.5))),
+                                              (1, 1, 2, 0, 0, 2)),
+    # ragged tiles and several boundary-pass blocks per face
+    "smooth_3d_66x53x40_tanh": lambda: with_bc(_stretched_box((66, 53, 40)), ALL),
+}
+
+
+def _stretched_box(n):
+    spec, _ = W.random_smooth_periodic(3, 8)
+    faces = tuple(W.tanh_faces(n[d], centre=0.3, depth=0.4, hi=n[d] / 64) for d in range(3))
+    spec = dataclasses.replace(spec, n=n, hi=tuple(float(v) / 64 for v in n), faces=faces)
+    return spec, _resample(spec)
+
+
+STRETCHED_PAIRS = [(name, k, r) for name, make in STRETCHED.items() for k in ("fused", "split")
+                   for r in ("weno5", "first") if k == "fused" or make()[0].ndim == 3]
+
+
+@pytest.mark.parametrize("name,kernel,recon", STRETCHED_PAIRS)
+def test_cbc_on_stretched_cells(name, kernel, recon):
+    spec, w = STRETCHED[name]()
+    say(f"[cbc stretched {recon}] {name} {spec.n} bc={spec.bc} kernel={kernel}")
+    r, q1 = rhs_and_step(spec, w, kernel, recon)
+    qo, ro, qn = oracle_rhs_and_step(spec, w, recon)
+    err = rhs_err(r, ro, qo, spec)
+    e1 = rel_linf(q1, qn, spec)
+    say(f"    rhs err {err.max():.2e}, one-step rel Linf {e1.max():.2e}")
+    bar = step_bar(rounding_spread(spec, oracle.prim_to_cons_field(spec, w), 1, cfl=0.3, recon=ORACLE_RECON[recon]))
+    assert err.max() <= 1e-12 and (e1 <= bar).all(), (e1, bar)
+
+
+@pytest.mark.parametrize("kernel", ["fused", "split"])
+def test_cbc_on_stretched_cells_200_steps(kernel):
+    spec, w = STRETCHED["bubble_3d_tanh"]()
+    say(f"[cbc stretched 200 steps] {spec.n} kernel={kernel}")
+    s = mfc.Solver(spec, kernel=KERNELS[kernel])
+    q = s.upload(oracle.prim_to_cons_field(spec, w))
+    s.run(q, 200, cfl=0.3)
+    s.check()
+    q0 = oracle.prim_to_cons_field(spec, w)
+    qn, t, st = oracle.run(spec, q0, 200, cfl=0.3)
+    assert st == oracle.OK
+    assert abs(s.time()[0] - t) <= 1e-12 * t
+    e = rel_l1(q.cpu().numpy(), qn, spec)
+    say(f"    200-step rel L1 {e.max():.2e}")
+    run_parity(e, spec, q0, 200, cfl=0.3)
+
+
 @pytest.mark.parametrize("kernel", sorted(KERNELS))
 def test_cbc_200_steps_3d(kernel):
     spec, w = CASES["smooth_3d_corners"]()
@@ -218,6 +279,24 @@ def test_cbc_fp32_error():
     ei = rel_linf(qg, qn, spec, floor_mom=acoustic_floor(spec, q0))
     say(f"[cbc fp32] rel L1 {e1.max():.2e}, rel Linf {ei.max():.2e}")
     assert e1.max() <= 1e-5 and ei.max() <= 1e-4
+
+
+@pytest.mark.parametrize("kernel", ["fused", "split"])
+def test_cbc_fp32_error_on_stretched_cells(kernel):
+    """As above on the tanh-stretched 3D bubble with every face
+    characteristic, 30 steps."""
+    spec, w = STRETCHED["bubble_3d_tanh"]()
+    s = mfc.Solver(spec, kernel=KERNELS[kernel], precision=mfc.MFC_FP32_MIXED)
+    q = s.upload(oracle.prim_to_cons_field(spec, w))
+    s.run(q, 30, cfl=0.3)
+    s.check()
+    q0 = oracle.prim_to_cons_field(spec, w)
+    qn, _, st = oracle.run(spec, q0, 30, cfl=0.3)
+    assert st == oracle.OK
+    qg = q.double().cpu().numpy()
+    e1 = rel_l1(qg, qn, spec, floor_mom=acoustic_floor(spec, q0))
+    say(f"[cbc fp32 stretched {kernel}] rel L1 {e1.max():.2e}")
+    assert e1.max() <= 1e-4
 
 
 @pytest.mark.parametrize("bc", [ALL, (2, 0, 1, 1, 0, 2)])

@@ -351,3 +351,70 @@ def test_routed_linear_step_matches_oracle():
     err = rel_linf(qd.cpu().numpy(), qo, spec)
     say(f"[route step] rel Linf {err.max():.2e}")
     assert err.max() <= 1e-12, err
+
+
+# Characteristic faces (Sec. 3.3) with the routed reconstruction: the split
+# kernels keep the normal terms of their own (routed) reconstruction for the
+# boundary pass, so routing and boundary treatment compose as in the oracle.
+ALL_CHAR = (2, 2, 2, 2, 2, 2)
+
+
+def _characteristic(sw):
+    import dataclasses
+    spec, w = sw
+    return dataclasses.replace(spec, bc=ALL_CHAR), w
+
+
+CHAR_ROUTED = {
+    "bubble_3d_37x21x19": (lambda: _characteristic(W.bubble_collapse_3d(n=(37, 21, 19))), 2),
+    "smooth_3d_18": (lambda: _characteristic(W.random_smooth_periodic(3, 18)), 0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CHAR_ROUTED))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_characteristic_routing_nothing_is_weno(name, prec):
+    make, steps = CHAR_ROUTED[name]
+    spec, w = make()
+    say(f"[route none, characteristic faces] {name} {prec}")
+    q = oracle_state(spec, w, steps)
+    P = {"fp64": mfc.MFC_FP64, "fp32": mfc.MFC_FP32_MIXED}[prec]
+    a = gpu_rhs(spec, q, "split", P)
+    b = gpu_rhs(spec, q, "split", P, params32(1), tau=2.0)
+    assert np.array_equal(a, b)
+
+
+def test_characteristic_routing_everything_is_the_linear_scheme():
+    spec, w = CHAR_ROUTED["smooth_3d_18"][0]()
+    q = oracle_state(spec, w)
+    got = gpu_rhs(spec, q, "split", params=params32(1), tau=-1.0)
+    ref, st = oracle.rhs(spec, q, oracle.RECON_LINEAR)
+    assert st == oracle.OK
+    err = rhs_err(got, ref, q, spec)
+    say(f"[route all, characteristic faces] rhs err {err.max():.2e}")
+    assert err.max() <= 1e-12, err
+
+
+def test_characteristic_routed_rhs_matches_oracle():
+    """As test_routed_rhs_matches_oracle, with every face characteristic."""
+    make, steps = CHAR_ROUTED["bubble_3d_37x21x19"]
+    spec, w = make()
+    q = oracle_state(spec, w, steps)
+    params = golden_params()
+    P = ind.smooth_probability(spec, q, params)
+    Pv = P[~np.isnan(P)]
+    for tau in tau_candidates(Pv, 2e-3, lo=0.02)[:40:4]:
+        ref, st, _ = ind.rhs_learned(spec, q, params, tau)
+        if st == oracle.OK:
+            break
+    assert st == oracle.OK
+    skip = ambiguous_cells(spec, P, tau, 2e-3)
+    frac = (Pv > tau).mean()
+    say(f"[route net, characteristic faces] tau {tau:.4f}, routed to linear {frac:.3f}, "
+        f"cells left out {skip.mean():.4f}")
+    assert 0.02 < frac < 0.95 and skip.mean() < 0.2
+    got = gpu_rhs(spec, q, "split", params=params, tau=tau)
+    err = masked_rhs_err(got, ref, q, spec, skip)
+    say(f"    rhs err {err.max():.2e}")
+    assert err.max() <= 1e-12, err
+
