@@ -45,18 +45,20 @@ FLOPS_PER_CELL_UPDATE_2D = 1561
 # read the stage input (56 B), read q^n on stages 2 and 3 (56 B), write the
 # result (56 B): (112 + 168 + 168) / 3.
 BYTES_PER_CELL_UPDATE = (112 + 168 + 168) / 3
-# The split path's two kernels.  x+y kernel: conservative->primitive 28 and
-# two directions of 870 -> 1769 flops; reads the stage input (56 B) and, on
-# stages 2-3 where it forms the x+y part of the stage combination, q^n
-# (56 B), and writes that x+y part (7 values, 56 B): (112 + 168 + 168) / 3 B
-# averaged over a step's three stages.  z kernel: the remaining
-# 2669 - 1769 = 900 flops (one direction, the source, the stage update);
-# reads the stage input and the x+y part, writes the result: 3 x 56 B (the
-# first stage of a CFL step reads its stage input a second time, which the
-# algorithmic count leaves out).
-SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences, x+y stage combination)", flops=1769,
+# The split path's two kernels.  x+y kernel: conservative->primitive 28, two
+# directions of 870 and the stage combination 28 (it forms q + dt L_xy in
+# the first stage and a q^n + b (q + dt L_xy) in the others) -> 1797 flops;
+# reads the stage input (56 B) and, on stages 2-3, q^n (56 B), and writes
+# that x+y part (7 values, 56 B): (112 + 168 + 168) / 3 B averaged over a
+# step's three stages.  z kernel: the remaining 2669 - 1797 = 872 flops (one
+# direction, the source, the z part of the update); reads the stage input
+# and the x+y part, writes the result: 3 x 56 B.  In a run of CFL steps the
+# step size is known before each first stage (the previous step's last z
+# pass reduces the wave speeds it writes); only the run's first step reads
+# its stage input a second time in the z pass, which the count leaves out.
+SPLIT = {0: dict(name="k_xy (x+y reconstruction, HLLC, flux differences, x+y stage combination)", flops=1797,
                  bytes=(112 + 168 + 168) / 3),
-         1: dict(name="k_z (z reconstruction, HLLC, source, stage update)", flops=2669 - 1769,
+         1: dict(name="k_z (z reconstruction, HLLC, source, stage update)", flops=2669 - 1797,
                  bytes=3 * 56)}
 # The library's kernel events bracket the launches of every tenth step of
 # the timed region.
@@ -132,33 +134,28 @@ def error_vs_reference(spec, w, make_solver, steps, mfc, weights, tau, reference
 
 
 def timed_run(torch, mfc, solver, q, steps, warmup, cfl):
-    """Advance q by `warmup` untimed and `steps` timed SSP-RK3 steps; the
-    library's kernel events cover every KERNEL_TIMING_STRIDE-th timed step.
-    Returns the elapsed seconds and (ms, launches) of both kernel slots."""
-    for _ in range(warmup):
-        solver.step(q, cfl=cfl)
+    """Advance q by `warmup` untimed and `steps` timed SSP-RK3 steps, the
+    timed ones as one run (mfc_run: on the split path each step's size comes
+    from the wave speeds its predecessor's last stage reduced); the library's
+    kernel events cover every KERNEL_TIMING_STRIDE-th timed step (events
+    between all launches would lengthen every step by about 4 %).  Returns
+    the elapsed seconds and (ms, launches) of both kernel slots."""
+    solver.run(q, warmup, cfl=cfl)
     torch.cuda.synchronize()
     solver.check()
     mfc.mfc_kernel_time(solver.h, 0)   # nothing recorded before the timed region
     mfc.mfc_kernel_time(solver.h, 1)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mfc.mfc_set_kernel_timing(solver.h, True, KERNEL_TIMING_STRIDE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for i in range(steps):
-        # the library's per-launch HIP events bracket the kernels of every
-        # KERNEL_TIMING_STRIDE-th step: events between all launches would
-        # lengthen every step by about 4 %
-        sample = i % KERNEL_TIMING_STRIDE == 0
-        if sample:
-            mfc.mfc_set_kernel_timing(solver.h, True)
-        solver.step(q, cfl=cfl)
-        if sample:
-            mfc.mfc_set_kernel_timing(solver.h, False)
+    solver.run(q, steps, cfl=cfl)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    mfc.mfc_set_kernel_timing(solver.h, False)
     k0 = mfc.mfc_kernel_time(solver.h, 0)
     k1 = mfc.mfc_kernel_time(solver.h, 1)
     solver.check()

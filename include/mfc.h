@@ -214,7 +214,14 @@ int mfc_max_wavespeed(mfc_grid *g, const void *q, double *smax_host, void *strea
  * synchronisation, to that caller-owned device double. */
 int mfc_rk3_step(mfc_grid *g, void *q, double cfl, double dt, double *dt_used_dev, void *stream);
 
-/* nsteps calls of mfc_rk3_step (dt_used_dev NULL), enqueued back to back. */
+/* nsteps SSP-RK3 steps as by mfc_rk3_step (dt_used_dev NULL), enqueued back
+ * to back.  MFC_KERNEL_SPLIT with cfl > 0 and no characteristic face: the
+ * z pass of each step's last stage also reduces the wave speeds of the
+ * state it writes (the next step's q^n), so the next step's size is set
+ * before its first stage, whose x+y pass then forms its part of the stage
+ * combination (q + dt L_xy, the z pass adding dt L_z) instead of the z pass
+ * reading q^n again.  The step sizes are those of single mfc_rk3_step calls
+ * on the same states, bit for bit; the states agree to rounding. */
 int mfc_run(mfc_grid *g, void *q, int nsteps, double cfl, double dt, void *stream);
 
 /* Synchronise and read the accumulated simulated time and the last step
@@ -226,15 +233,18 @@ int mfc_reset_time(mfc_grid *g, void *stream);
  * non-physical cell since the last check, and clear the flag. */
 int mfc_check(mfc_grid *g, void *stream);
 
-/* Kernel timing: while enabled, every launch of the right-hand-side kernels
- * is bracketed by HIP events on the launch stream.  Slot 0 is the main
+/* Kernel timing: while enabled, launches of the right-hand-side kernels are
+ * bracketed by HIP events on the launch stream.  Slot 0 is the main
  * right-hand-side kernel (the fused kernel, the x+y kernel of the split
  * path, or the whole staged sequence); slot 1 is the z + stage-update kernel
- * of the split path.  Disabling stops the recording and keeps what was
- * recorded, so timing can cover a sample of the launches (say every tenth
- * step).  mfc_kernel_time synchronises, returns the summed duration (ms) and
- * number of timed launches of that slot since the last call for it, and
- * resets them.  slot outside [0, 1] gives MFC_E_ARG. */
+ * of the split path.  enable = 0 stops the recording and keeps what was
+ * recorded; enable = 1 times every launch; enable = N > 1 times every
+ * launch of mfc_rhs and those of every N-th SSP-RK3 step of mfc_rk3_step and
+ * mfc_run, counted from this call (the first step is timed), so that a
+ * sample of a long run is timed without events between all its launches.
+ * enable < 0 gives MFC_E_ARG.  mfc_kernel_time synchronises, returns the
+ * summed duration (ms) and number of timed launches of that slot since the
+ * last call for it, and resets them.  slot outside [0, 1] gives MFC_E_ARG. */
 int mfc_set_kernel_timing(mfc_grid *g, int enable);
 int mfc_kernel_time(mfc_grid *g, int slot, double *ms_total, int64_t *launches);
 

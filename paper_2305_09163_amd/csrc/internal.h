@@ -36,8 +36,13 @@ struct mfc_grid {
     float *mlp = nullptr;      // learned indicator parameters (FP32, flat order of mlp.h)
     float logit_tau = 0.0f;    // routing threshold on the indicator's logit
 
-    // kernel timing, per slot (0: main right-hand-side kernel, 1: z kernel)
+    // kernel timing, per slot (0: main right-hand-side kernel, 1: z kernel);
+    // stride N records the launches of every N-th step (timing_step counts
+    // the steps since timing was enabled; timing_skip is set for the others)
     bool timing = false;
+    int timing_stride = 1;
+    int64_t timing_step = 0;
+    bool timing_skip = false;
     std::vector<hipEvent_t> ev[2];  // pairs (start, stop)
     size_t ev_used[2] = {0, 0};
 };
@@ -81,8 +86,12 @@ int launch_rhs_staged(mfc_grid *h, const void *q, const void *q0, void *out, int
                       const double *dt_dev, hipStream_t s);
 int launch_rhs_fused(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
                      const double *dt_dev, hipStream_t s);
+// Split path: cfl > 0 reduces the wave speeds of q in the x+y pass and sets
+// the step size before the z pass (the first stage of a CFL step); zmax
+// non-null (a last stage) has the z pass reduce the wave speeds of the state
+// it writes into zmax, split_z_partials(g) maxima for the next step.
 int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
-                     const double *dt_dev, hipStream_t s, double cfl = 0.0);
+                     const double *dt_dev, hipStream_t s, double cfl = 0.0, double *zmax = nullptr);
 
 // Split right-hand side (mode 0) without a handle: 3D uniform cells,
 // WENO5/WENO3/first order as g.order says, no learned routing and no
@@ -93,6 +102,8 @@ int launch_rhs_split_raw(const Grid &g, bool fp32, const void *q, void *out, voi
 // Split path: number of x+y workgroups of one launch (each writes one
 // wave-speed partial when the step size is computed inside the launch).
 int64_t split_xy_blocks(const Grid &g);
+// Split path: number of wave-speed partials the z pass writes (one per wavefront).
+int64_t split_z_partials(const Grid &g, bool fp32);
 
 // Reduce nblocks partial maxima, set the step size (cfl > 0: from the
 // maxima; else dt) and advance the accumulated time, on the device.

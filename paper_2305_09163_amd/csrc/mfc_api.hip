@@ -32,7 +32,7 @@ int hip_status(hipError_t e, const char *what)
 
 void timing_begin(mfc_grid *h, hipStream_t s, int slot)
 {
-    if (!h->timing) return;
+    if (!h->timing || h->timing_skip) return;
     auto &ev = h->ev[slot];
     if (h->ev_used[slot] + 2 > ev.size()) {
         for (int t = 0; t < 64; t++) {
@@ -46,7 +46,7 @@ void timing_begin(mfc_grid *h, hipStream_t s, int slot)
 
 void timing_end(mfc_grid *h, hipStream_t s, int slot)
 {
-    if (!h->timing || h->ev_used[slot] + 2 > h->ev[slot].size()) return;
+    if (!h->timing || h->timing_skip || h->ev_used[slot] + 2 > h->ev[slot].size()) return;
     (void)hipEventRecord(h->ev[slot][h->ev_used[slot] + 1], s);
     h->ev_used[slot] += 2;
 }
@@ -371,11 +371,11 @@ int by_ndim(int ndim, F f)
 }
 
 int rhs_dispatch(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
-                 const double *dt_dev, hipStream_t s, double cfl = 0.0)
+                 const double *dt_dev, hipStream_t s, double cfl = 0.0, double *zmax = nullptr)
 {
     int st;
     if (h->desc.kernel == MFC_KERNEL_STAGED) st = launch_rhs_staged(h, q, q0, out, mode, dt, dt_dev, s);
-    else if (h->desc.kernel == MFC_KERNEL_SPLIT) st = launch_rhs_split(h, q, q0, out, mode, dt, dt_dev, s, cfl);
+    else if (h->desc.kernel == MFC_KERNEL_SPLIT) st = launch_rhs_split(h, q, q0, out, mode, dt, dt_dev, s, cfl, zmax);
     else st = launch_rhs_fused(h, q, q0, out, mode, dt, dt_dev, s);
     if (st == MFC_OK && has_cbc(h)) st = launch_cbc(h, q, out, mode, dt, dt_dev, s);
     return st;
@@ -533,7 +533,8 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
         if (words) alloc(&h->cbc_fv, words * elem_bytes(h));
         g.cbc_fv = h->cbc_fv;
     }
-    h->partial_len = std::max<int64_t>(kReduceBlocks, desc->ndim == 3 ? split_xy_blocks(g) : 0);
+    h->partial_len = std::max<int64_t>(
+        kReduceBlocks, desc->ndim == 3 ? std::max(split_xy_blocks(g), split_z_partials(g, is_fp32(h))) : 0);
     alloc((void **)&h->partial, h->partial_len * 8);
     alloc((void **)&h->scalars, 4 * 8);
     alloc((void **)&h->flag, 8);
@@ -646,21 +647,50 @@ int mfc_max_wavespeed(mfc_grid *h, const void *q, double *smax_host, void *strea
     return MFC_OK;
 }
 
-int mfc_rk3_step(mfc_grid *h, void *qv, double cfl, double dt, double *dt_used_dev, void *stream)
+namespace {
+
+// Split path, CFL steps of one run: the z pass of a step's last stage can
+// reduce the wave speeds of q^{n+1} as it writes it (the x+y pass of the
+// next step's first stage would reduce the same values to the same
+// maxima), so that the next step's size is known before its first stage and
+// that stage's x+y pass forms its part of the combination.  Not with
+// characteristic faces, whose boundary pass changes boundary cells after the
+// z pass.
+bool carries_wavespeed(const mfc_grid *h, double cfl)
 {
-    if (bad_handle(h) || !qv) return fail(MFC_E_ARG, "null argument");
-    if (!(cfl > 0.0) && !(dt > 0.0)) return fail(MFC_E_ARG, "need cfl > 0 or dt > 0");
-    if (!std::isfinite(cfl) || !std::isfinite(dt)) return fail(MFC_E_ARG, "cfl and dt must be finite");
-    int st = set_device(h);
-    if (st) return st;
-    hipStream_t s = (hipStream_t)stream;
-    void *q = qv, *A = h->stage_a, *B = h->stage_b;
+    return cfl > 0.0 && h->desc.kernel == MFC_KERNEL_SPLIT && !has_cbc(h);
+}
+
+// One SSP-RK3 step.  carried_in: the wave-speed partials of q^n are in
+// h->partial (written by the previous step's last stage); carry_out: have
+// this step's last stage write those of q^{n+1}.
+int rk3_step_launches(mfc_grid *h, void *q, double cfl, double dt, double *dt_used_dev, hipStream_t s,
+                      bool carried_in, bool carry_out);
+
+int rk3_step(mfc_grid *h, void *q, double cfl, double dt, double *dt_used_dev, hipStream_t s, bool carried_in,
+             bool carry_out)
+{
+    // with a timing stride, only every stride-th step's launches are timed
+    h->timing_skip = h->timing && (h->timing_step++ % h->timing_stride) != 0;
+    const int st = rk3_step_launches(h, q, cfl, dt, dt_used_dev, s, carried_in, carry_out);
+    h->timing_skip = false;
+    return st;
+}
+
+int rk3_step_launches(mfc_grid *h, void *q, double cfl, double dt, double *dt_used_dev, hipStream_t s,
+                      bool carried_in, bool carry_out)
+{
+    int st = MFC_OK;
+    void *A = h->stage_a, *B = h->stage_b;
     const double *dt_dev = h->scalars + 1;
     // the split kernels read boundary neighbours through the boundary
     // condition itself (the values a ghost fill writes) and need no fill
     const bool fill = h->desc.kernel != MFC_KERNEL_SPLIT;
     if (fill && (st = fill_ghosts(h, q, s))) return st;
-    if (h->desc.kernel == MFC_KERNEL_SPLIT && cfl > 0.0) {
+    if (carried_in) {
+        launch_step_begin(h, h->partial, (int)split_z_partials(h->g, is_fp32(h)), cfl, 0.0, s);
+        if ((st = rhs_dispatch(h, q, q, A, 1, 0.0, dt_dev, s))) return st;
+    } else if (h->desc.kernel == MFC_KERNEL_SPLIT && cfl > 0.0) {
         // the x+y pass of the first stage reduces the wave speeds of q^n and
         // the step size is set before its z pass, the first to use it
         if ((st = rhs_dispatch(h, q, q, A, 1, 0.0, dt_dev, s, cfl))) return st;
@@ -676,19 +706,38 @@ int mfc_rk3_step(mfc_grid *h, void *qv, double cfl, double dt, double *dt_used_d
     if (fill && (st = fill_ghosts(h, A, s))) return st;
     if ((st = rhs_dispatch(h, A, q, B, 2, 0.0, dt_dev, s))) return st;
     if (fill && (st = fill_ghosts(h, B, s))) return st;
-    if ((st = rhs_dispatch(h, B, q, q, 3, 0.0, dt_dev, s))) return st;
+    if ((st = rhs_dispatch(h, B, q, q, 3, 0.0, dt_dev, s, 0.0, carry_out ? h->partial : nullptr))) return st;
     if (dt_used_dev) hipLaunchKernelGGL(k_copy_dt, dim3(1), dim3(64), 0, s, h->scalars, dt_used_dev);
     return hip_status(hipGetLastError(), "rk3 step launch");
+}
+
+int check_step_args(mfc_grid *h, const void *q, double cfl, double dt)
+{
+    if (bad_handle(h) || !q) return fail(MFC_E_ARG, "null argument");
+    if (!(cfl > 0.0) && !(dt > 0.0)) return fail(MFC_E_ARG, "need cfl > 0 or dt > 0");
+    if (!std::isfinite(cfl) || !std::isfinite(dt)) return fail(MFC_E_ARG, "cfl and dt must be finite");
+    return set_device(h);
+}
+
+}  // namespace
+
+int mfc_rk3_step(mfc_grid *h, void *q, double cfl, double dt, double *dt_used_dev, void *stream)
+{
+    int st = check_step_args(h, q, cfl, dt);
+    if (st) return st;
+    return rk3_step(h, q, cfl, dt, dt_used_dev, (hipStream_t)stream, false, false);
 }
 
 int mfc_run(mfc_grid *h, void *q, int nsteps, double cfl, double dt, void *stream)
 {
     if (nsteps < 0) return fail(MFC_E_ARG, "nsteps must be >= 0");
-    for (int n = 0; n < nsteps; n++) {
-        int st = mfc_rk3_step(h, q, cfl, dt, nullptr, stream);
-        if (st) return st;
-    }
-    return MFC_OK;
+    if (nsteps == 0) return MFC_OK;
+    int st = check_step_args(h, q, cfl, dt);
+    if (st) return st;
+    const bool carry = carries_wavespeed(h, cfl);
+    for (int n = 0; n < nsteps && st == MFC_OK; n++)
+        st = rk3_step(h, q, cfl, dt, nullptr, (hipStream_t)stream, carry && n > 0, carry && n + 1 < nsteps);
+    return st;
 }
 
 int mfc_time(mfc_grid *h, double *t_host, double *last_dt_host, void *stream)
@@ -735,7 +784,10 @@ int mfc_check(mfc_grid *h, void *stream)
 int mfc_set_kernel_timing(mfc_grid *h, int enable)
 {
     if (bad_handle(h)) return fail(MFC_E_ARG, "handle is NULL");
+    if (enable < 0) return fail(MFC_E_ARG, "enable must be >= 0");
     h->timing = enable != 0;   // what was recorded stays until mfc_kernel_time reads it
+    h->timing_stride = enable > 1 ? enable : 1;
+    h->timing_step = 0;
     return MFC_OK;
 }
 

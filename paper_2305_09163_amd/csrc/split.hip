@@ -598,12 +598,18 @@ static_assert(kRing<false> >= 1 && kRing<false> <= 4 && kRing<true> >= 1 && kRin
 // part of the stage combination (dt unknown then): out = q + dt (L_xy + L_z),
 // reading the stage input again.  Otherwise out = (x+y part) + s L_z with
 // s = cb dt (a folded stage) or 1 (a bare right-hand side).
-template <class T, bool ROUTE, int ORDER, bool STRETCH, bool KEEP, bool REREAD>
+// SMAX (the last stage of a step followed by another CFL step in the same
+// run): the kernel also reduces the wave speeds of the state it writes, the
+// next step's q^n, exactly as the x+y pass of a first stage does from the
+// stored values (the same conversion in the same arithmetic, so the same
+// maxima), one partial maximum per wavefront in smax_partial.
+template <class T, bool ROUTE, int ORDER, bool STRETCH, bool KEEP, bool REREAD, bool SMAX = false>
 __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
     k_z(Grid g, const T *__restrict__ q, T *__restrict__ out, const T *__restrict__ lxy, int mode, double dt,
         const double *__restrict__ dt_dev, int *__restrict__ flag, const float *__restrict__ mlpw, float logit_tau,
-        T sqrt_eps)
+        T sqrt_eps, double *__restrict__ smax_partial)
 {
+    static_assert(!(SMAX && REREAD), "the wave speeds are reduced in a step's last stage");
     // window of W = 2H - 1 planes; the kRing oldest in the LDS ring
     constexpr int H = kHalo<ORDER>, OFF = kOff<ORDER>, W = 2 * H - 1;
     constexpr int kRing = mfc::kRing<ROUTE> < W - 1 ? mfc::kRing<ROUTE> : W - 1, kZReg = W - kRing;
@@ -617,16 +623,20 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
     __shared__ __align__(16) typename std::conditional<ROUTE, mlp::Params, char>::type s_mlp;
     __shared__ __align__(16) uint16_t s_feat[ROUTE ? NZT * 16 : 1];
     __shared__ T s_ring[kRing][NV][NZT];
-    if constexpr (ROUTE) {
-        // every lane of a wavefront takes part in the classification: lanes
-        // past a ragged edge march a duplicate of the last column
-        mlp::stage_params(s_mlp, nullptr, mlpw, threadIdx.x, NZT);
-        __syncthreads();
+    if constexpr (ROUTE || SMAX) {
+        // every lane of a wavefront takes part in the classification or the
+        // reduction: lanes past a ragged edge march a duplicate of the last
+        // column (their maxima are those of that column)
+        if constexpr (ROUTE) {
+            mlp::stage_params(s_mlp, nullptr, mlpw, threadIdx.x, NZT);
+            __syncthreads();
+        }
         gx = min(gx, g.n[0] - 1);
         gy = min(gy, g.n[1] - 1);
     } else if (!own) {
         return;   // no barriers in this variant
     }
+    double smax = 0.0;
     uint16_t *scratch = s_feat + (ROUTE ? (threadIdx.x / 64) * 64 * 16 : 0);
     const int lane = threadIdx.x % 64, t = threadIdx.x;
     const int z0 = bz * kLZ<T>, z1 = min(z0 + kLZ<T>, g.n[2]);
@@ -760,8 +770,25 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
 #pragma unroll
                     for (int v = 0; v < NV; v++) out[v * g.vstride + c] = qb[v] + hdt * (lx[v] + L[v]);
                 } else {
+                    T r[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; v++) out[v * g.vstride + c] = lx[v] + sz * L[v];
+                    for (int v = 0; v < NV; v++) {
+                        r[v] = lx[v] + sz * L[v];
+                        out[v * g.vstride + c] = r[v];
+                    }
+                    if constexpr (SMAX) {   // |u_d| + c of the stored state (non-uniform cells: over dx_d)
+                        T w[NV];
+                        cons_to_prim<3, T>(g, r, w);
+                        double Gam, Pi;
+                        mixture<double>(g, double(w[6]), Gam, Pi);
+                        const double cs = sqrtT(sound2<double>(Gam, Pi, double(w[0]) + double(w[1]), double(w[5])));
+                        const int ci[3] = {gx, gy, k};
+#pragma unroll
+                        for (int d = 0; d < 3; d++) {
+                            const double a = __builtin_fabs(double(w[2 + d])) + cs;
+                            smax = __builtin_fmax(smax, STRETCH ? a * inv_width(g, d, ci[d]) : a);
+                        }
+                    }
                 }
             }
 #pragma unroll
@@ -782,6 +809,12 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
     };
     if (MFC_Z_ALT && (bz & 1)) march(std::integral_constant<int, -1>{});
     else march(std::integral_constant<int, 1>{});
+    if constexpr (SMAX) {   // wavefront maximum, one partial per wavefront
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) smax = __builtin_fmax(smax, __shfl_xor(smax, o, 64));
+        if (lane == 0)
+            smax_partial[((int64_t)(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * kZY + t / 64] = smax;
+    }
     if (bad) atomicOr(flag, 1);
 }
 
@@ -792,7 +825,7 @@ dim3 xy_grid(const Grid &g)
 
 template <class T, bool ROUTE, int ORDER, bool STRETCH = false, bool KEEP = false>
 int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt, const double *dt_dev, hipStream_t s,
-              double cfl)
+              double cfl, double *zmax)
 {
     const Grid &g = h->g;
     const dim3 gxy = xy_grid(g);
@@ -810,12 +843,22 @@ int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
     timing_end(h, s);
     if (partial) launch_step_begin(h, partial, (int)split_xy_blocks(g), cfl, 0.0, s);
     timing_begin(h, s, 1);
-    if (mode != 0 && !fold)
+    bool done = false;
+    if constexpr (!KEEP) {   // characteristic faces never carry the wave speeds (the boundary pass follows)
+        if (zmax && mode != 0 && fold) {
+            hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH, KEEP, false, true>), gz, dim3(kZX * kZY), 0, s, g, q,
+                               out, lxy, mode, dt, dt_dev, h->flag, h->mlp, h->logit_tau, se, zmax);
+            done = true;
+        }
+    }
+    if (done) {
+    } else if (mode != 0 && !fold) {
         hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH, KEEP, true>), gz, dim3(kZX * kZY), 0, s, g, q, out, lxy, mode,
-                           dt, dt_dev, h->flag, h->mlp, h->logit_tau, se);
-    else
+                           dt, dt_dev, h->flag, h->mlp, h->logit_tau, se, nullptr);
+    } else {
         hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH, KEEP, false>), gz, dim3(kZX * kZY), 0, s, g, q, out, lxy, mode,
-                           dt, dt_dev, h->flag, h->mlp, h->logit_tau, se);
+                           dt, dt_dev, h->flag, h->mlp, h->logit_tau, se, nullptr);
+    }
     timing_end(h, s, 1);
     return hip_status(hipGetLastError(), "split right-hand side launch");
 }
@@ -833,7 +876,7 @@ int rhs_split_raw(const Grid &g, const T *q, T *out, T *lxy, int *flag, hipStrea
     hipLaunchKernelGGL((k_xy<T, false, ORDER, false, false>), gxy, dim3(NT), 0, s, g, q, q, lxy, flag, nullptr, 0.f,
                        se, nullptr, 0, 0, 0.0, nullptr);
     hipLaunchKernelGGL((k_z<T, false, ORDER, false, false, false>), gz, dim3(kZX * kZY), 0, s, g, q, out, lxy, 0, 0.0,
-                       nullptr, flag, nullptr, 0.f, se);
+                       nullptr, flag, nullptr, 0.f, se, nullptr);
     return hip_status(hipGetLastError(), "split right-hand side launch");
 }
 
@@ -862,8 +905,14 @@ int64_t split_xy_blocks(const Grid &g)
     return (int64_t)b.x * b.y * b.z;
 }
 
+int64_t split_z_partials(const Grid &g, bool fp32)
+{
+    const int lz = fp32 ? kLZ<float> : kLZ<double>;
+    return (int64_t)((g.n[0] + kZX - 1) / kZX) * ((g.n[1] + kZY - 1) / kZY) * ((g.n[2] + lz - 1) / lz) * kZY;
+}
+
 int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int mode, double dt,
-                     const double *dt_dev, hipStream_t s, double cfl)
+                     const double *dt_dev, hipStream_t s, double cfl, double *zmax)
 {
     if (h->g.ndim != 3) return fail(MFC_E_UNSUPPORTED, "the split path is 3D only");
     const bool learned = h->desc.recon == MFC_RECON_LEARNED;
@@ -875,44 +924,44 @@ int launch_rhs_split(mfc_grid *h, const void *q, const void *q0, void *out, int 
     const bool f32 = h->desc.precision == MFC_FP32_MIXED;
     if (h->g.stretched && h->g.cbc_mask) {   // non-uniform cells with characteristic faces
         if (h->desc.recon == MFC_RECON_FIRST_ORDER)
-            return f32 ? rhs_split<float, false, 1, true, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                       : rhs_split<double, false, 1, true, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
-        return f32 ? rhs_split<float, false, 5, true, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                   : rhs_split<double, false, 5, true, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+            return f32 ? rhs_split<float, false, 1, true, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                       : rhs_split<double, false, 1, true, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
+        return f32 ? rhs_split<float, false, 5, true, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                   : rhs_split<double, false, 5, true, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
     }
     if (h->g.stretched) {   // non-uniform cells: WENO5 or first order (checked at init)
         if (h->desc.recon == MFC_RECON_FIRST_ORDER)
-            return f32 ? rhs_split<float, false, 1, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                       : rhs_split<double, false, 1, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
-        return f32 ? rhs_split<float, false, 5, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                   : rhs_split<double, false, 5, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+            return f32 ? rhs_split<float, false, 1, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                       : rhs_split<double, false, 1, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
+        return f32 ? rhs_split<float, false, 5, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                   : rhs_split<double, false, 5, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
     }
     if (h->g.cbc_mask) {   // characteristic faces (WENO5, WENO3, first order or routed; checked at init)
         if (learned)
-            return f32 ? rhs_split<float, true, 5, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                       : rhs_split<double, true, 5, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+            return f32 ? rhs_split<float, true, 5, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                       : rhs_split<double, true, 5, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
         if (h->desc.recon == MFC_RECON_WENO3)
-            return f32 ? rhs_split<float, false, 3, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                       : rhs_split<double, false, 3, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+            return f32 ? rhs_split<float, false, 3, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                       : rhs_split<double, false, 3, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
         if (h->desc.recon == MFC_RECON_FIRST_ORDER)
-            return f32 ? rhs_split<float, false, 1, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                       : rhs_split<double, false, 1, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
-        return f32 ? rhs_split<float, false, 5, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                   : rhs_split<double, false, 5, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+            return f32 ? rhs_split<float, false, 1, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                       : rhs_split<double, false, 1, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
+        return f32 ? rhs_split<float, false, 5, false, true>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                   : rhs_split<double, false, 5, false, true>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
     }
     switch (h->desc.recon) {
     case MFC_RECON_LEARNED:
-        return f32 ? rhs_split<float, true, 5>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                   : rhs_split<double, true, 5>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+        return f32 ? rhs_split<float, true, 5>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                   : rhs_split<double, true, 5>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
     case MFC_RECON_WENO3:
-        return f32 ? rhs_split<float, false, 3>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                   : rhs_split<double, false, 3>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+        return f32 ? rhs_split<float, false, 3>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                   : rhs_split<double, false, 3>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
     case MFC_RECON_FIRST_ORDER:
-        return f32 ? rhs_split<float, false, 1>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                   : rhs_split<double, false, 1>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+        return f32 ? rhs_split<float, false, 1>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                   : rhs_split<double, false, 1>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
     default:
-        return f32 ? rhs_split<float, false, 5>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl)
-                   : rhs_split<double, false, 5>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl);
+        return f32 ? rhs_split<float, false, 5>(h, fq, fq0, fo, mode, dt, dt_dev, s, cfl, zmax)
+                   : rhs_split<double, false, 5>(h, dq, dq0, dout, mode, dt, dt_dev, s, cfl, zmax);
     }
 }
 

@@ -249,8 +249,8 @@ def mfc_check(h, stream=None):
     _check(lib().mfc_check(h, _stream(stream)), "mfc_check")
 
 
-def mfc_set_kernel_timing(h, enable: bool):
-    _check(lib().mfc_set_kernel_timing(h, int(enable)), "mfc_set_kernel_timing")
+def mfc_set_kernel_timing(h, enable: bool, stride: int = 1):
+    _check(lib().mfc_set_kernel_timing(h, int(stride) if enable else 0), "mfc_set_kernel_timing")
 
 
 def mfc_kernel_time(h, slot: int = 0):
