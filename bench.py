@@ -66,16 +66,17 @@ KERNEL_TIMING_STRIDE = 10
 # Measured HBM traffic per launch (bytes) of the split path's kernels on the
 # 128^3 bubble: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each
 # scaled by its reading for a copy kernel of known size (FETCH_SIZE x 2.00,
-# WRITE_SIZE x 1.00), averaged over the three stages of a step (the z
-# kernel's first stage reads its stage input twice).  Valid only for the
-# kernel sources they were taken on; any change to those files turns
-# `traffic` back to null.
+# WRITE_SIZE x 1.00), averaged over the three stages of a step of a run
+# (in which every first stage's z pass reads only what the others read; the
+# run's first step, which reads its stage input twice, left out).  Valid
+# only for the kernel sources they were taken on; any change to those files
+# turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h", "charbc.h")
-TRAFFIC = {"sha256": "33cd438c4431b6ebc3304b7d41bc4f09b4c58d919db5e1f99ba2ad6ce30e6183",
-           ("split", "fp32", 128, 0): (124.71e6, 62.42e6),
-           ("split", "fp32", 128, 1): (159.18e6, 61.58e6),
-           ("split", "fp64", 128, 0): (238.28e6, 127.50e6),
-           ("split", "fp64", 128, 1): (329.31e6, 123.85e6)}
+TRAFFIC = {"sha256": "075f8141f1c8b04d092cd6d1e152872f7473f7cc3505c87224812471a509b688",
+           ("split", "fp32", 128, 0): (126.25e6, 62.41e6),
+           ("split", "fp32", 128, 1): (143.68e6, 61.50e6),
+           ("split", "fp64", 128, 0): (238.10e6, 127.51e6),
+           ("split", "fp64", 128, 1): (287.75e6, 123.17e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
