@@ -358,15 +358,20 @@ int mfc_batch_layout(const mfc_batch *b, int run, int64_t *nvar, int64_t padded[
 int mfc_batch_cells(const mfc_batch *b, int64_t *cells, int *nrun);
 
 /* One SSP-RK3 step of every run in place on q[0..count-1] (device arrays of
- * the run layouts; ghost cells are filled by the step).  Step size per run:
+ * the run layouts).  Neighbours past a domain face are taken through the
+ * run's boundary conditions (the values a ghost fill would write, bit for
+ * bit): ghost cells are neither read nor written.  Step size per run:
  * cfl * min_d dx_d / (max wave speed of that run), on the device. */
 int mfc_batch_step(mfc_batch *b, void *const *q, double cfl, void *stream);
 
-/* nsteps steps.  With use_graph != 0, steps are replayed from a HIP graph
- * that captures up to 64 steps of the whole ensemble; it is captured on the
- * first call and reused while q, cfl, the chunk length and the
- * configuration stay the same.  Kernel timing (mfc_batch_set_timing) turns
- * graph replay off. */
+/* nsteps steps.  Within the call each step's size comes from the wave
+ * speeds the previous step's last stage reduced over the state it wrote
+ * (the first step, and the first of each graph replay, reduce their own):
+ * the same sizes and states, bit for bit, as nsteps mfc_batch_step calls.
+ * With use_graph != 0, steps are replayed from a HIP graph that captures up
+ * to 64 steps of the whole ensemble; it is captured on the first call and
+ * reused while q, cfl, the chunk length and the configuration stay the
+ * same.  Kernel timing (mfc_batch_set_timing) turns graph replay off. */
 int mfc_batch_run(mfc_batch *b, void *const *q, int nsteps, double cfl, int use_graph, void *stream);
 
 /* Choose the launch configuration: time the first-stage kernel (which reads

@@ -1,16 +1,22 @@
 // Batched ensembles of independent 2D runs (uneven grid sizes) advanced
 // together: every kernel of an SSP-RK3 step (Sec. 3.4) covers all runs at
-// once, so one step of the whole ensemble is eight launches, which
+// once, so one step of the whole ensemble is five launches (four when the
+// previous step of the same run call supplied the wave speeds), which
 // mfc_batch_run captures once into a HIP graph and replays.
 //
-//   k_batch_ghosts     ghost face slabs of every run (Sec. 3.3)
 //   k_batch_wavespeed  per-run maxima of max_d(|u_d| + c)
 //   k_batch_dt         per-run time step from the CFL number (Sec. 1)
 //   k_batch_stage      the right-hand side of eq. (fvmdis) (Sec. 3.1-3.2.1)
 //                      and the stage combination; a persistent kernel: a
 //                      fixed set of workgroups walks the flat list of
 //                      (run, tile) work items, 16 x 16 (or autotuned) tiles
-//                      of the LDS-staged x/y sweep.
+//                      of the LDS-staged x/y sweep.  It reads neighbours
+//                      past a domain face through the boundary rule
+//                      (bc_cell: the values a ghost fill would write, bit
+//                      for bit), so no ghost fill runs; in the last stage
+//                      of a step followed by another of the same call it
+//                      also reduces the wave speeds of the state it writes,
+//                      for that step's size.
 // Runs differ only through their descriptors (sizes, strides, dx, fluids,
 // boundaries), so a run advanced in the batch and the same run advanced
 // alone by the single-grid path execute the same arithmetic.
@@ -32,55 +38,8 @@ struct RunDev {
     Grid g;
     T *q;          // caller's state (step input and output)
     T *a, *b;      // stage registers q^(1), q^(2)
-    int bc[4];
     int tiles_x;   // for the stage kernel's tile decode (set per tile shape)
 };
-
-// ---------------------------------------------------------------- ghosts
-// Work index -> (run, ghost value) through the prefix offsets of the runs.
-template <class T>
-__global__ void __launch_bounds__(kBT) k_batch_ghosts(const RunDev<T> *__restrict__ runs, const int64_t *__restrict__ goff,
-                                                      int nrun, int which)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= goff[nrun]) return;
-    int lo = 0, hi = nrun - 1;  // largest r with goff[r] <= t
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (goff[mid] <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    const RunDev<T> &R = runs[lo];
-    const Grid &g = R.g;
-    T *q = which == 0 ? R.q : (which == 1 ? R.a : R.b);
-    int64_t r = t - goff[lo];
-    // per run: dimension 0 slabs (2*NG*ny per variable) then dimension 1 (2*NG*nx)
-    const int nv = 6;
-    const int64_t cx = (int64_t)2 * NG * g.n[1] * nv;
-    const int d = r < cx ? 0 : 1;
-    if (d == 1) r -= cx;
-    const int o1 = d == 0 ? 1 : 0;
-    const int n1 = g.n[o1], n = g.n[d];
-    const int64_t per_var = (int64_t)2 * NG * n1;
-    const int v = (int)(r / per_var);
-    r %= per_var;
-    const int a = (int)(r % n1);
-    r /= n1;
-    const int l = 1 + (int)(r % NG);
-    const int side = (int)(r / NG);
-    int c[2], src[2];
-    c[o1] = src[o1] = a;
-    if (side == 0) {
-        c[d] = -l;
-        src[d] = R.bc[2 * d] == MFC_BC_PERIODIC ? n - l : 0;
-    } else {
-        c[d] = n - 1 + l;
-        src[d] = R.bc[2 * d + 1] == MFC_BC_PERIODIC ? l - 1 : n - 1;
-    }
-    const int64_t dst = (int64_t)(c[1] + NG) * g.stride[1] + (c[0] + NG);
-    const int64_t s = (int64_t)(src[1] + NG) * g.stride[1] + (src[0] + NG);
-    q[v * g.vstride + dst] = q[v * g.vstride + s];
-}
 
 // ------------------------------------------------------------ wave speed
 template <class T>
@@ -119,13 +78,23 @@ __global__ void __launch_bounds__(kBT) k_batch_wavespeed(const RunDev<T> *__rest
 }
 
 // Per-run step size and accumulated time: scal[3 r + 0..2] = smax, dt, t.
-__global__ void k_batch_dt(const double *__restrict__ partial, double *__restrict__ scal, const double *__restrict__ dxmin,
-                           int nrun, double cfl)
+// The maximum comes from the wave-speed partials, or (carried) from the
+// maxima the previous step's last stage accumulated in cmax, kept as the
+// bit patterns of non-negative doubles (which order as integers); either
+// way cmax is cleared for the next accumulation.
+__global__ void k_batch_dt(const double *__restrict__ partial, unsigned long long *__restrict__ cmax,
+                           double *__restrict__ scal, const double *__restrict__ dxmin, int nrun, double cfl,
+                           int carried)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrun) return;
     double m = 0.0;
-    for (int b = 0; b < kWsBlocks; b++) m = __builtin_fmax(m, partial[r * kWsBlocks + b]);
+    if (carried) {
+        m = __longlong_as_double((long long)cmax[r]);
+    } else {
+        for (int b = 0; b < kWsBlocks; b++) m = __builtin_fmax(m, partial[r * kWsBlocks + b]);
+    }
+    cmax[r] = 0ull;
     const double dt = cfl * dxmin[r] / m;
     scal[3 * r + 0] = m;
     scal[3 * r + 1] = dt;
@@ -166,7 +135,8 @@ constexpr int kBatchWaves =
 template <int TX, int TY, class T>
 __global__ void __launch_bounds__(kBT, (kBatchWaves<TX, TY, T>))
     k_batch_stage(const RunDev<T> *__restrict__ runs, const int *__restrict__ item_run, const int *__restrict__ item_tile,
-                  int nitems, const double *__restrict__ scal, int stage, int xcd, int *__restrict__ flag)
+                  int nitems, const double *__restrict__ scal, int stage, int xcd, int *__restrict__ flag,
+                  unsigned long long *__restrict__ cmax)
 {
     using S = Tile2<TX, TY, T>;
     constexpr int NV = 6, A = 5, E = 4;
@@ -203,8 +173,12 @@ __global__ void __launch_bounds__(kBT, (kBatchWaves<TX, TY, T>))
         const int xmax = g.n[0] + NG - 1, ymax = g.n[1] + NG - 1;
         const int gx = x0 + tx, gy = y0 + ty;
         const bool own = gx < g.n[0] && gy < g.n[1];
+        // cell (i, j) of the tile's window through the boundary rule (cells
+        // past a ragged tile edge load a duplicate whose results are dropped)
+        auto bx = [&](int i) { return bc_cell(min(i, xmax), g.n[0], g.bc[0], g.bc[1]); };
+        auto by = [&](int j) { return bc_cell(min(j, ymax), g.n[1], g.bc[2], g.bc[3]); };
         T wk[NV];
-        bad |= load6<T>(g, q, min(gx, xmax), min(gy, ymax), wk);
+        bad |= load6<T>(g, q, bx(gx), by(gy), wk);
 #pragma unroll
         for (int v = 0; v < NV; v++) s_plane[v][ty + NG][tx + NG] = wk[v];
         for (int h = tid; h < S::NHALO; h += kBT) {
@@ -220,7 +194,7 @@ __global__ void __launch_bounds__(kBT, (kBatchWaves<TX, TY, T>))
                 lj = r < NG ? r : TY + r;
             }
             T w[NV];
-            bad |= load6<T>(g, q, min(x0 + li - NG, xmax), min(y0 + lj - NG, ymax), w);
+            bad |= load6<T>(g, q, bx(x0 + li - NG), by(y0 + lj - NG), w);
 #pragma unroll
             for (int v = 0; v < NV; v++) s_plane[v][lj][li] = w[v];
         }
@@ -289,6 +263,7 @@ __global__ void __launch_bounds__(kBT, (kBatchWaves<TX, TY, T>))
             divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
         }
         L[A] += alpha_source<T>(g, wk[A], wk[E]) * divu;
+        double smax_item = 0.0;
         if (own) {
             const int64_t c = (int64_t)(gy + NG) * g.stride[1] + (gx + NG);
             // every operand before the first store (out may alias q0)
@@ -298,8 +273,26 @@ __global__ void __launch_bounds__(kBT, (kBatchWaves<TX, TY, T>))
                 a0[v] = q0[v * g.vstride + c];
                 a1[v] = q[v * g.vstride + c];
             }
+            T r[NV];
 #pragma unroll
-            for (int v = 0; v < NV; v++) out[v * g.vstride + c] = ca * a0[v] + cb * (a1[v] + hdt * L[v]);
+            for (int v = 0; v < NV; v++) {
+                r[v] = ca * a0[v] + cb * (a1[v] + hdt * L[v]);
+                out[v * g.vstride + c] = r[v];
+            }
+            if (cmax) {   // max_d |u_d| + c of the stored state, as k_batch_wavespeed forms it
+                T wr[NV];
+                cons_to_prim<2, T>(g, r, wr);
+                double Gam, Pi;
+                mixture<double>(g, double(wr[5]), Gam, Pi);
+                const double cs = sqrtT(sound2<double>(Gam, Pi, double(wr[0]) + double(wr[1]), double(wr[4])));
+                smax_item = __builtin_fmax(__builtin_fabs(double(wr[2])), __builtin_fabs(double(wr[3]))) + cs;
+            }
+        }
+        if (cmax) {   // wavefront maximum of the item, one atomic per wavefront
+            double m = smax_item;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) m = __builtin_fmax(m, __shfl_xor(m, o, 64));
+            if ((tid & 63) == 0) atomicMax(&cmax[run], (unsigned long long)__double_as_longlong(m));
         }
         // the next item overwrites s_plane only after every thread passed the
         // barrier above; s_pair and s_flux after two more
@@ -339,12 +332,11 @@ struct mfc_batch {
     std::vector<Grid> grids;
     std::vector<void *> stage;        // 2 per run
     void *runs = nullptr;             // RunDev<T>[nrun] (device)
-    int64_t *goff = nullptr;          // ghost prefix offsets [nrun + 1] (device)
-    int64_t ghost_total = 0;
     int64_t cells = 0;
     int *items[kNumShapes][2] = {};   // item_run, item_tile per shape (device)
     int nitems[kNumShapes] = {};
     double *partial = nullptr;        // [nrun * kWsBlocks]
+    unsigned long long *cmax = nullptr;  // [nrun] carried wave-speed maxima (bit patterns)
     double *scal = nullptr;           // [3 * nrun]
     double *dxmin = nullptr;          // [nrun]
     int *flag = nullptr;
@@ -381,7 +373,6 @@ int upload_runs(mfc_batch *b, void *const *q)
         h[r].q = (T *)q[r];
         h[r].a = (T *)b->stage[2 * r];
         h[r].b = (T *)b->stage[2 * r + 1];
-        for (int f = 0; f < 4; f++) h[r].bc[f] = b->desc[r].bc[f];
         h[r].tiles_x = (b->grids[r].n[0] + tx - 1) / tx;
     }
     // earlier steps may still read the descriptors
@@ -415,7 +406,7 @@ unsigned stage_groups(const mfc_batch *b)
 }
 
 template <class T>
-void launch_stage(mfc_batch *b, int st, hipStream_t s)
+void launch_stage(mfc_batch *b, int st, hipStream_t s, unsigned long long *cmax = nullptr)
 {
     const RunDev<T> *runs = (const RunDev<T> *)b->runs;
     const int sh = b->tune.shape, nitems = b->nitems[sh], xcd = b->tune.xcd;
@@ -425,11 +416,11 @@ void launch_stage(mfc_batch *b, int st, hipStream_t s)
     if (b->timing && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
         (void)hipEventRecord(e0, s);
     if (sh == 0)
-        hipLaunchKernelGGL((k_batch_stage<16, 16, T>), grid, block, 0, s, runs, ir, it, nitems, b->scal, st, xcd, b->flag);
+        hipLaunchKernelGGL((k_batch_stage<16, 16, T>), grid, block, 0, s, runs, ir, it, nitems, b->scal, st, xcd, b->flag, cmax);
     else if (sh == 1)
-        hipLaunchKernelGGL((k_batch_stage<32, 8, T>), grid, block, 0, s, runs, ir, it, nitems, b->scal, st, xcd, b->flag);
+        hipLaunchKernelGGL((k_batch_stage<32, 8, T>), grid, block, 0, s, runs, ir, it, nitems, b->scal, st, xcd, b->flag, cmax);
     else
-        hipLaunchKernelGGL((k_batch_stage<64, 4, T>), grid, block, 0, s, runs, ir, it, nitems, b->scal, st, xcd, b->flag);
+        hipLaunchKernelGGL((k_batch_stage<64, 4, T>), grid, block, 0, s, runs, ir, it, nitems, b->scal, st, xcd, b->flag, cmax);
     if (e1) {
         (void)hipEventRecord(e1, s);
         b->ev.emplace_back(e0, e1);
@@ -438,25 +429,37 @@ void launch_stage(mfc_batch *b, int st, hipStream_t s)
     }
 }
 
+// One step of every run.  carried_in: the per-run maxima of this step's
+// input were accumulated in cmax by the previous step's last stage;
+// carry_out: have this step's last stage accumulate those of its output.
 template <class T>
-int enqueue_step(mfc_batch *b, double cfl, hipStream_t s)
+int enqueue_step(mfc_batch *b, double cfl, hipStream_t s, bool carried_in, bool carry_out)
 {
     const RunDev<T> *runs = (const RunDev<T> *)b->runs;
-    const unsigned gblocks = (unsigned)((b->ghost_total + kBT - 1) / kBT);
-    hipLaunchKernelGGL((k_batch_ghosts<T>), dim3(gblocks), dim3(kBT), 0, s, runs, b->goff, b->nrun, 0);
-    hipLaunchKernelGGL((k_batch_wavespeed<T>), dim3(b->nrun * kWsBlocks), dim3(kBT), 0, s, runs, b->partial, b->flag);
-    hipLaunchKernelGGL(k_batch_dt, dim3((b->nrun + 63) / 64), dim3(64), 0, s, b->partial, b->scal, b->dxmin, b->nrun, cfl);
+    if (!carried_in)
+        hipLaunchKernelGGL((k_batch_wavespeed<T>), dim3(b->nrun * kWsBlocks), dim3(kBT), 0, s, runs, b->partial,
+                           b->flag);
+    hipLaunchKernelGGL(k_batch_dt, dim3((b->nrun + 63) / 64), dim3(64), 0, s, b->partial, b->cmax, b->scal, b->dxmin,
+                       b->nrun, cfl, carried_in ? 1 : 0);
     launch_stage<T>(b, 1, s);
-    hipLaunchKernelGGL((k_batch_ghosts<T>), dim3(gblocks), dim3(kBT), 0, s, runs, b->goff, b->nrun, 1);
     launch_stage<T>(b, 2, s);
-    hipLaunchKernelGGL((k_batch_ghosts<T>), dim3(gblocks), dim3(kBT), 0, s, runs, b->goff, b->nrun, 2);
-    launch_stage<T>(b, 3, s);
+    launch_stage<T>(b, 3, s, carry_out ? b->cmax : nullptr);
     return hip_status(hipGetLastError(), "batch step launch");
 }
 
-int enqueue(mfc_batch *b, double cfl, hipStream_t s)
+int enqueue(mfc_batch *b, double cfl, hipStream_t s, bool carried_in = false, bool carry_out = false)
 {
-    return b->precision == MFC_FP32_MIXED ? enqueue_step<float>(b, cfl, s) : enqueue_step<double>(b, cfl, s);
+    return b->precision == MFC_FP32_MIXED ? enqueue_step<float>(b, cfl, s, carried_in, carry_out)
+                                          : enqueue_step<double>(b, cfl, s, carried_in, carry_out);
+}
+
+// n steps as one sequence: the first reduces its wave speeds itself, every
+// other takes them from its predecessor's last stage.
+int enqueue_steps(mfc_batch *b, int n, double cfl, hipStream_t s)
+{
+    int st = MFC_OK;
+    for (int k = 0; k < n && st == MFC_OK; k++) st = enqueue(b, cfl, s, k > 0, k + 1 < n);
+    return st;
 }
 
 int collect_timing(mfc_batch *b)
@@ -493,7 +496,7 @@ int mfc_batch_free(mfc_batch *b)
     for (int sh = 0; sh < kNumShapes; sh++)
         for (int k = 0; k < 2; k++)
             if (b->items[sh][k]) (void)hipFree(b->items[sh][k]);
-    for (void *p : {b->runs, (void *)b->goff, (void *)b->partial, (void *)b->scal, (void *)b->dxmin, (void *)b->flag})
+    for (void *p : {b->runs, (void *)b->cmax, (void *)b->partial, (void *)b->scal, (void *)b->dxmin, (void *)b->flag})
         if (p) (void)hipFree(p);
     delete b;
     return MFC_OK;
@@ -537,7 +540,6 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
         delete b;
         return fail(MFC_E_HIP, "device query failed");
     }
-    std::vector<int64_t> goff(count + 1, 0);
     std::vector<double> dxmin(count);
     for (int r = 0; r < count; r++) {
         const mfc_grid_desc &d = descs[r];
@@ -551,6 +553,7 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
         g.p[2] = 1;
         g.off[0] = g.off[1] = NG;
         g.off[2] = 0;
+        for (int f = 0; f < 6; f++) g.bc[f] = f < 4 ? d.bc[f] : MFC_BC_EXTRAP;   // read by index (bc_cell)
         g.stride[0] = 1;
         g.stride[1] = g.p[0];
         g.stride[2] = (int64_t)g.p[0] * g.p[1];
@@ -572,9 +575,7 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
         b->grids.push_back(g);
         dxmin[r] = g.dxmin;
         b->cells += (int64_t)g.n[0] * g.n[1];
-        goff[r + 1] = goff[r] + (int64_t)2 * NG * (g.n[1] + g.n[0]) * 6;
     }
-    b->ghost_total = goff[count];
     hipError_t e = hipSuccess;
     auto alloc = [&](void **p, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc(p, bytes);
@@ -583,7 +584,7 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
     for (int r = 0; r < count; r++)
         for (int k = 0; k < 2; k++) alloc(&b->stage[2 * r + k], (size_t)6 * b->grids[r].vstride * elem(b));
     alloc(&b->runs, sizeof(RunDev<double>) * count);
-    alloc((void **)&b->goff, sizeof(int64_t) * (count + 1));
+    alloc((void **)&b->cmax, sizeof(unsigned long long) * count);
     alloc((void **)&b->partial, sizeof(double) * count * kWsBlocks);
     alloc((void **)&b->scal, sizeof(double) * 3 * count);
     alloc((void **)&b->dxmin, sizeof(double) * count);
@@ -604,7 +605,7 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
         if (e == hipSuccess) e = hipMemcpy(b->items[sh][0], ir.data(), sizeof(int) * ir.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(b->items[sh][1], it.data(), sizeof(int) * it.size(), hipMemcpyHostToDevice);
     }
-    if (e == hipSuccess) e = hipMemcpy(b->goff, goff.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->cmax, 0, sizeof(unsigned long long) * count);   // set-up, not a graph node
     if (e == hipSuccess) e = hipMemcpy(b->dxmin, dxmin.data(), sizeof(double) * count, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_batch_reset, dim3((3 * count + 255) / 256), dim3(256), 0, 0, b->scal, 3 * count, b->flag);
@@ -655,7 +656,7 @@ int mfc_batch_step(mfc_batch *b, void *const *q, double cfl, void *stream)
     if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(MFC_E_ARG, "cfl must be > 0");
     int st = bind(b, q);
     if (st) return st;
-    return enqueue(b, cfl, (hipStream_t)stream);
+    return enqueue_steps(b, 1, cfl, (hipStream_t)stream);
 }
 
 int mfc_batch_run(mfc_batch *b, void *const *q, int nsteps, double cfl, int use_graph, void *stream)
@@ -666,11 +667,7 @@ int mfc_batch_run(mfc_batch *b, void *const *q, int nsteps, double cfl, int use_
     int st = bind(b, q);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
-    if (!use_graph || b->timing) {
-        for (int n = 0; n < nsteps; n++)
-            if ((st = enqueue(b, cfl, s))) return st;
-        return MFC_OK;
-    }
+    if (!use_graph || b->timing) return enqueue_steps(b, nsteps, cfl, s);
     const int chunk = std::min(nsteps, kMaxGraphSteps);
     if (chunk == 0) return MFC_OK;
     if (!b->graph || b->graph_cfl != cfl || b->graph_steps != chunk) {
@@ -682,7 +679,7 @@ int mfc_batch_run(mfc_batch *b, void *const *q, int nsteps, double cfl, int use_
         hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            for (int n = 0; n < chunk && st == MFC_OK; n++) st = enqueue(b, cfl, cs);
+            st = enqueue_steps(b, chunk, cfl, cs);   // each replay starts from its own wave speeds
             e = hipStreamEndCapture(cs, &graph);
         }
         if (e == hipSuccess && st == MFC_OK) e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
@@ -701,9 +698,7 @@ int mfc_batch_run(mfc_batch *b, void *const *q, int nsteps, double cfl, int use_
         hipError_t e = hipGraphLaunch(b->graph, s);
         if (e != hipSuccess) return hip_status(e, "graph launch");
     }
-    for (; done < nsteps; done++)
-        if ((st = enqueue(b, cfl, s))) return st;
-    return MFC_OK;
+    return enqueue_steps(b, nsteps - done, cfl, s);
 }
 
 int mfc_batch_autotune(mfc_batch *b, void *const *q, int reps, mfc_batch_tune *best, double *ms_table, void *stream)
@@ -727,13 +722,6 @@ int mfc_batch_autotune(mfc_batch *b, void *const *q, int reps, mfc_batch_tune *b
             for (int x = 0; x < 2 && st == MFC_OK; x++) {
                 b->tune = mfc_batch_tune{sh, gr, x};
                 if ((st = bind(b, q))) break;
-                if (b->precision == MFC_FP32_MIXED) {
-                    hipLaunchKernelGGL((k_batch_ghosts<float>), dim3((unsigned)((b->ghost_total + kBT - 1) / kBT)),
-                                       dim3(kBT), 0, s, (const RunDev<float> *)b->runs, b->goff, b->nrun, 0);
-                } else {
-                    hipLaunchKernelGGL((k_batch_ghosts<double>), dim3((unsigned)((b->ghost_total + kBT - 1) / kBT)),
-                                       dim3(kBT), 0, s, (const RunDev<double> *)b->runs, b->goff, b->nrun, 0);
-                }
                 b->timing = false;
                 if (b->precision == MFC_FP32_MIXED) launch_stage<float>(b, 1, s);  // warm-up
                 else launch_stage<double>(b, 1, s);

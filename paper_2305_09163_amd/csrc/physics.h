@@ -18,6 +18,8 @@
 
 #include <type_traits>
 
+#include "../../include/mfc.h"   // MFC_BC_* (boundary kinds)
+
 namespace mfc {
 
 constexpr int NG = 3;  // ghost layers: WENO5 reads 2 cells past the face cell
@@ -71,6 +73,19 @@ __device__ __forceinline__ void store_normal_terms(const Grid &g, int c1, int n1
 #pragma unroll
     for (int v = 0; v < 7; v++) dst[v] = L[v];
     dst[7] = divu;
+}
+
+// Interior cell whose value the ghost position i (-NG <= i < n + NG) holds
+// after the ghost fill of Sec. 3.3: the adjacent interior cell
+// (extrapolation) or the cell one period away (periodic).  The split and
+// batched kernels read every neighbour through this map and never read a
+// ghost cell, which gives the values a filled ghost layer holds, bit for
+// bit, with no fill pass.
+__device__ __forceinline__ int bc_cell(int i, int n, int lo, int hi)
+{
+    if (i < 0) return lo == MFC_BC_PERIODIC ? i + n : 0;
+    if (i >= n) return hi == MFC_BC_PERIODIC ? i - n : n - 1;
+    return i;
 }
 
 // ---------------------------------------------------------------- reciprocal

@@ -124,19 +124,6 @@ __device__ __forceinline__ int64_t offset(const Grid &g, int i, int j, int k)
     return (int64_t)(k + g.off[2]) * g.stride[2] + (int64_t)(j + g.off[1]) * g.stride[1] + (i + g.off[0]);
 }
 
-// Interior cell whose value the ghost position i (-NG <= i < n + NG) holds
-// after the ghost fill of Sec. 3.3: the adjacent interior cell
-// (extrapolation) or the cell one period away (periodic).  The split kernels
-// read every neighbour through this map and never read a ghost cell, which
-// gives the values a filled ghost layer holds, bit for bit, with no fill
-// pass.
-__device__ __forceinline__ int bc_cell(int i, int n, int lo, int hi)
-{
-    if (i < 0) return lo == MFC_BC_PERIODIC ? i + n : 0;
-    if (i >= n) return hi == MFC_BC_PERIODIC ? i - n : n - 1;
-    return i;
-}
-
 // Both face values of a cell from the ORDER values of its stencil, starting
 // at st with stride s (WENO5, WENO3 or first order, Sec. 3.2).
 template <int ORDER, class T>

@@ -177,3 +177,32 @@ def test_full_ensemble_sampled_runs_match_single_grid():
         (q1, t1), = single_runs([runs[r]], "fp32", 5)
         assert torch.equal(interior(qs[r]), interior(q1)), r
         assert b.time()[r] == t1
+
+
+def test_run_equals_single_steps_and_reads_no_ghost_cell():
+    """mfc_batch_run takes each step's size from the wave speeds its
+    predecessor's last stage reduced; single mfc_batch_step calls reduce them
+    at the start of every step: the same sizes and states, bit for bit.  The
+    stage kernel reads neighbours past a face through the boundary rule, so
+    NaN in every ghost cell changes nothing and stays where it is."""
+    runs = ensemble(SIZES, seed0=600)
+    specs = [s for s, _ in runs]
+    br, bs = mfc.Batch(specs), mfc.Batch(specs)
+    qr = br.states_from_prim([w for _, w in runs])
+    qs = [q.clone() for q in qr]
+    ghost = []
+    for q in qr:
+        g = torch.ones(q.shape, dtype=torch.bool, device=q.device)
+        g[:, :, 3:-3, 3:-3] = False
+        q[g] = float("nan")
+        ghost.append(g)
+    br.run(qr, 5, 0.3, use_graph=False)
+    for _ in range(5):
+        bs.step(qs, 0.3)
+    br.check()
+    bs.check()
+    say(f"[batch run vs steps] times {br.time()[:2]} / {bs.time()[:2]}")
+    assert br.time() == bs.time()
+    for r in range(len(qr)):
+        assert torch.equal(interior(qr[r]), interior(qs[r])), r
+        assert torch.isnan(qr[r][ghost[r]]).all(), r
