@@ -67,7 +67,7 @@ enum {
  * (on non-uniform cells, the derivative of the quadratic through the
  * boundary cell's centre and the next two) and every amplitude whose wave
  * enters the domain set to zero (Allaire model; with the learned routing on
- * the split kernel only; not in batches). */
+ * the split kernel only). */
 enum { MFC_BC_EXTRAP = 0, MFC_BC_PERIODIC = 1, MFC_BC_CHARACTERISTIC = 2 };
 enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
 /* Reconstruction of the primitive variables at the faces (Sec. 3.2):
@@ -319,7 +319,10 @@ int mfc_trainer_infer(mfc_trainer *t, const uint16_t *features, int64_t n, float
  * runs, each run takes its own CFL step size (Sec. 1) on the device, and the
  * right-hand side of every run is the one mfc_rhs defines.  A run advanced in
  * a batch gives the same bits as the same run advanced alone with
- * mfc_rk3_step (MFC_KERNEL_FUSED, same precision and cfl).
+ * mfc_rk3_step (MFC_KERNEL_FUSED, same precision and cfl), except a run with
+ * characteristic faces, which the batch's stage kernel applies itself and
+ * the single-grid kernels in a boundary pass: the same scheme, rounded in
+ * another order.
  *
  * State arrays stay owned by the caller: run r is a device array of the 2D
  * state layout above (nvar 6, padded (n[0] + 6, n[1] + 6, 1)).  The batch

@@ -24,6 +24,7 @@
 #include <map>
 #include <new>
 
+#include "charbc.h"
 #include "internal.h"
 
 namespace mfc {
@@ -123,6 +124,22 @@ __device__ __forceinline__ bool load6(const Grid &g, const T *__restrict__ q, in
     const bool bad = cons_to_prim<2, T>(g, qc, w);
     const int outside = (i < 0 || i >= g.n[0]) + (j < 0 || j >= g.n[1]);
     return bad && outside <= 1;
+}
+
+// Characteristic rates (charbc.h, Sec. 3.3) of the boundary cell at tile
+// position (r, c) on face SIDE of dimension D, from the cell and the next
+// two cells into the domain in the tile's LDS plane.
+template <int D, int SIDE, class T, int PY, int PX>
+__device__ __forceinline__ bool tile_char_rate(const Grid &g, const T (&pl)[6][PY][PX], int r, int c, T inv_dx,
+                                               T *rate)
+{
+    constexpr int sg = SIDE == 0 ? 1 : -1;
+    T W[3][6];
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+#pragma unroll
+        for (int v = 0; v < 6; v++) W[j][v] = D == 0 ? pl[v][r][c + sg * j] : pl[v][r + sg * j][c];
+    return char_rate<2, D, SIDE, T>(g, W[0], W[1], W[2], inv_dx, one_sided<T>(g, D, SIDE), rate);
 }
 
 // LDS of a tile (plane, face-value pairs, fluxes): the FP64 64 x 4 tile
@@ -231,6 +248,23 @@ __global__ void __launch_bounds__(kBT, (kBatchWaves<TX, TY, T>))
             for (int v = 0; v < NV; v++) L[v] = (s_flux[v][f] - s_flux[v][f + 1]) * idx;
             divu = (s_flux[NV][f + 1] - s_flux[NV][f]) * idx;
         }
+        // Characteristic faces (Sec. 3.3): the boundary cell of such a face
+        // takes the characteristic rates in place of its terms normal to it.
+        // The rates of x faces are taken here, while s_plane is this item's
+        // for every thread, and put in place of the x terms after the y
+        // sweep; every other cell sums its terms exactly as the single-grid
+        // kernel does.
+        const int xside = !own ? -1
+                               : (gx == 0 && g.bc[0] == MFC_BC_CHARACTERISTIC)
+                                     ? 0
+                                     : ((gx == g.n[0] - 1 && g.bc[1] == MFC_BC_CHARACTERISTIC) ? 1 : -1);
+        const int yside = !own ? -1
+                               : (gy == 0 && g.bc[2] == MFC_BC_CHARACTERISTIC)
+                                     ? 0
+                                     : ((gy == g.n[1] - 1 && g.bc[3] == MFC_BC_CHARACTERISTIC) ? 1 : -1);
+        T xrate[NV];
+        if (xside == 0) bad |= tile_char_rate<0, 0>(g, s_plane, ty + NG, tx + NG, idx, xrate);
+        else if (xside == 1) bad |= tile_char_rate<0, 1>(g, s_plane, ty + NG, tx + NG, idx, xrate);
         for (int p = tid; p < S::NPY; p += kBT) {
             const int c = p % TX, r = p / TX;
             const int li = c + NG;
@@ -261,6 +295,24 @@ __global__ void __launch_bounds__(kBT, (kBatchWaves<TX, TY, T>))
 #pragma unroll
             for (int v = 0; v < NV; v++) L[v] += (s_flux[v][f] - s_flux[v][f + TX]) * idy;
             divu += (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
+        }
+        if (xside >= 0 || yside >= 0) {   // boundary cells of characteristic faces
+            // the y terms again (the x ones: the sum minus them), each
+            // replaced by the face's rates where the cell is on such a face
+            // (s_plane stays this item's until the barrier at the end of it)
+            const int f = ty * TX + tx;
+            T yt[NV], rate[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) yt[v] = (s_flux[v][f] - s_flux[v][f + TX]) * idy;
+            const T dy = (s_flux[NV][f + TX] - s_flux[NV][f]) * idy;
+            if (yside == 0) bad |= tile_char_rate<1, 0>(g, s_plane, ty + NG, tx + NG, idy, rate);
+            else if (yside == 1) bad |= tile_char_rate<1, 1>(g, s_plane, ty + NG, tx + NG, idy, rate);
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const T xs = xside >= 0 ? xrate[v] : L[v] - yt[v];
+                L[v] = xs + (yside >= 0 ? rate[v] : yt[v]);
+            }
+            divu = (xside >= 0 ? T(0) : divu - dy) + (yside >= 0 ? T(0) : dy);
         }
         L[A] += alpha_source<T>(g, wk[A], wk[E]) * divu;
         double smax_item = 0.0;
@@ -521,9 +573,11 @@ int mfc_batch_init(const mfc_grid_desc *descs, int count, mfc_batch **out)
             if (d.n[k] < 3 || d.n[k] > (1 << 15)) return fail(MFC_E_ARG, "n must be in [3, 32768]");
             if (!(d.hi[k] > d.lo[k])) return fail(MFC_E_ARG, "hi must exceed lo");
             const int a = d.bc[2 * k], c = d.bc[2 * k + 1];
-            if ((a != MFC_BC_EXTRAP && a != MFC_BC_PERIODIC) || (c != MFC_BC_EXTRAP && c != MFC_BC_PERIODIC) ||
-                ((a == MFC_BC_PERIODIC) != (c == MFC_BC_PERIODIC)))
+            auto known = [](int x) { return x == MFC_BC_EXTRAP || x == MFC_BC_PERIODIC || x == MFC_BC_CHARACTERISTIC; };
+            if (!known(a) || !known(c) || ((a == MFC_BC_PERIODIC) != (c == MFC_BC_PERIODIC)))
                 return fail(MFC_E_ARG, "bad boundary conditions");
+            if ((a == MFC_BC_CHARACTERISTIC || c == MFC_BC_CHARACTERISTIC) && d.model != MFC_MODEL_ALLAIRE)
+                return fail(MFC_E_UNSUPPORTED, "characteristic boundaries take the Allaire model");
         }
         for (int f = 0; f < 2; f++)
             if (!(d.gamma[f] > 1.0) || !(d.pi_inf[f] >= 0.0)) return fail(MFC_E_ARG, "bad fluid parameters");

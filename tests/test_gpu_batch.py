@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from parity_util import rel_linf, rounding_spread, step_bar
+from parity_util import acoustic_floor, rel_l1, rel_linf, rounding_spread, run_parity, step_bar
 from paper_2305_09163_amd import mfc
 from paper_2305_09163_amd import workloads as W
 
@@ -206,3 +206,62 @@ def test_run_equals_single_steps_and_reads_no_ghost_cell():
     for r in range(len(qr)):
         assert torch.equal(interior(qr[r]), interior(qs[r])), r
         assert torch.isnan(qr[r][ghost[r]]).all(), r
+
+
+def _with_bc(sw, bc):
+    import dataclasses
+    spec, w = sw
+    return dataclasses.replace(spec, bc=bc), w
+
+
+CHAR_RUNS = [
+    _with_bc(W.droplet_shock_2d((19, 23), W.SEED + 700), (2, 2, 2, 2, 0, 0)),
+    _with_bc(W.droplet_shock_2d((33, 27), W.SEED + 701), (2, 0, 0, 2, 0, 0)),
+    _with_bc(W.droplet_shock_2d((24, 40), W.SEED + 702), (1, 1, 2, 2, 0, 0)),
+    _with_bc(W.droplet_shock_2d((40, 17), W.SEED + 703), (0, 0, 0, 0, 0, 0)),
+]
+
+
+def test_batch_characteristic_faces_match_oracle():
+    """Characteristic faces (Sec. 3.3) in batched runs, beside runs without
+    them: the stage kernel takes the boundary cells' characteristic rates in
+    place of their normal terms, as the oracle does; each run after 1 and 20
+    steps against the oracle's run of the same run (FP64)."""
+    specs = [s for s, _ in CHAR_RUNS]
+    b = mfc.Batch(specs, precision=mfc.MFC_FP64)
+    qi = [oracle.prim_to_cons_field(s, w) for s, w in CHAR_RUNS]
+    qs = b.upload(qi)
+    done = 0
+    for n in (1, 20):
+        b.run(qs, n - done, 0.3, use_graph=n > 1)
+        done = n
+        b.check()
+        for r, (spec, _) in enumerate(CHAR_RUNS):
+            qo, t, st = oracle.run(spec, qi[r], n, cfl=0.3)
+            assert st == oracle.OK
+            got = qs[r].cpu().numpy()
+            if n == 1:
+                err = rel_linf(got, qo, spec)
+                bar = step_bar(rounding_spread(spec, qi[r], 1, cfl=0.3))
+                say(f"[batch characteristic] run {r} bc={spec.bc[:4]}: one step rel Linf {err.max():.2e}")
+                assert (err <= bar).all(), (r, err, bar)
+            else:
+                e = rel_l1(got, qo, spec)
+                say(f"[batch characteristic] run {r}: {n} steps rel L1 {e.max():.2e}")
+                run_parity(e, spec, qi[r], n, cfl=0.3)
+            assert abs(b.time()[r] - t) <= 1e-13 * t
+
+
+def test_batch_characteristic_faces_fp32():
+    specs = [s for s, _ in CHAR_RUNS]
+    b = mfc.Batch(specs, precision=mfc.MFC_FP32_MIXED)
+    qi = [oracle.prim_to_cons_field(s, w) for s, w in CHAR_RUNS]
+    qs = b.upload(qi)
+    b.run(qs, 20, 0.3)
+    b.check()
+    for r, (spec, _) in enumerate(CHAR_RUNS):
+        qo, _, st = oracle.run(spec, qi[r], 20, cfl=0.3)
+        assert st == oracle.OK
+        e = rel_l1(qs[r].double().cpu().numpy(), qo, spec, floor_mom=acoustic_floor(spec, qi[r]))
+        say(f"[batch characteristic fp32] run {r}: rel L1 {e.max():.2e}")
+        assert e.max() <= 1e-4, (r, e)
