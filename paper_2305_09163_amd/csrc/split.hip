@@ -20,13 +20,17 @@
 //         faces) and solves each z face once, forms the z flux differences
 //         and the z share of the source, and writes the stage result: the
 //         x+y part plus cb dt L_z (or L_xy + L_z for a bare right-hand side,
-//         q + dt (L_xy + L_z) in the first stage of a CFL step, whose dt is
-//         set between the two launches).
+//         q + dt (L_xy + L_z) in a first stage whose dt is set between the
+//         two launches from the x+y pass's wave-speed maxima).  In the last
+//         stage of a step followed by another of the same run it also
+//         reduces the wave speeds of the state it writes, which sets the
+//         next step's dt before that step starts.
 //
 // Neither kernel carries the other's state, so each fits its registers
 // without spilling; the price is one round trip of 7 values per cell through
 // HBM, and with the combination folded into the x+y pass the z pass reads
-// neither q^n nor its own stage input a second time.  Both kernels are instantiated for FP64 and for the FP32 storage form
+// neither q^n nor its own stage input a second time.  Both kernels are
+// instantiated for FP64 and for the FP32 storage form
 // (T = float; the x+y part is kept in the same type), and with the routed
 // reconstruction (ROUTE = true): every (cell, direction) is first classified by
 // the learned indicator of mlp.h, a whole wavefront at a time, and a smooth
@@ -197,11 +201,11 @@ struct RouteLds {
     static constexpr int own_words = (ROUTE && !in_flux) ? kFeatWords : 1;
 };
 
-// When smax_partial is not null (first stage of a step with a CFL step size)
-// the kernel also reduces max_d (|u_d| + c) over its interior cells, the
-// quantity of the CFL condition (Sec. 1), and writes one maximum per
-// workgroup: the step size is then set between this launch and the z pass,
-// which is the first to use it.
+// When smax_partial is not null (the first stage of a CFL step whose wave
+// speeds no earlier launch reduced) the kernel also reduces max_d (|u_d| + c)
+// over its interior cells, the quantity of the CFL condition (Sec. 1), and
+// writes one maximum per workgroup: the step size is then set between this
+// launch and the z pass, which is the first to use it.
 #ifndef MFC_XY_WAVES32
 #define MFC_XY_WAVES32 5
 #endif
@@ -821,8 +825,8 @@ int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
     const T se = T(__builtin_sqrt(g.eps));
     double *partial = cfl > 0.0 ? h->partial : nullptr;
     // the x+y pass forms its part of the stage combination whenever the
-    // stage's dt is known before it runs (not in the first stage of a CFL
-    // step, whose dt is set from that pass's wave-speed maxima)
+    // stage's dt is known before it runs (not in a first stage whose dt is
+    // set from that pass's own wave-speed maxima)
     const int fold = mode != 0 && !partial;
     timing_begin(h, s);
     hipLaunchKernelGGL((k_xy<T, ROUTE, ORDER, STRETCH, KEEP>), gxy, dim3(NT), 0, s, g, q, q0, lxy, h->flag, h->mlp,
