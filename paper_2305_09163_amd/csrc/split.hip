@@ -212,8 +212,12 @@ struct RouteLds {
 // the routed variant's LDS (network, feature exchange) admits two workgroups per CU
 // non-uniform cells read the tile's coefficient rows from LDS: the FP64
 // kernel then fits two workgroups per CU, the FP32 one four
-template <class T, bool ROUTE, bool STRETCH = false>
-constexpr int kXYWaves = ROUTE ? 2 : (STRETCH ? (sizeof(T) == 8 ? 2 : 4) : (sizeof(T) == 8 ? 3 : MFC_XY_WAVES32));
+// the FP32 kernel with characteristic faces runs four workgroups per CU (at
+// five its boundary rates spill 14 registers; 1.5 % faster measured)
+template <class T, bool ROUTE, bool STRETCH = false, bool KEEP = false>
+constexpr int kXYWaves = ROUTE ? 2
+                               : (STRETCH ? (sizeof(T) == 8 ? 2 : 4)
+                                          : (sizeof(T) == 8 ? 3 : (KEEP ? 4 : MFC_XY_WAVES32)));
 
 // The x+y pass holds the operands of its part of the stage combination in
 // registers from the start of each plane (FP64: their latency then overlaps
@@ -226,7 +230,7 @@ template <class T>
 constexpr bool kHoldFold = sizeof(T) == 8 ? MFC_XY_HOLD64 : 0;
 
 template <class T, bool ROUTE, int ORDER, bool STRETCH, bool KEEP>
-__global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
+__global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH, KEEP>))
     k_xy(Grid g, const T *__restrict__ q, const T *q0, T *__restrict__ lxy, int *__restrict__ flag,
          const float *__restrict__ mlpw, float logit_tau, T sqrt_eps, double *__restrict__ smax_partial,
          int mode, int fold, double dt, const double *__restrict__ dt_dev)
@@ -352,11 +356,16 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH>))
         // operands of the x+y part of the stage combination, held from here
         // to the end of the plane so that the q^n load overlaps its work:
         // the cell's stage input (before the next plane's fetch replaces it)
-        // and q^n
+        // and q^n.  The copy is kept ahead of the q^n loads (the empty asm):
+        // placed after them, its wait for the fetched values was also a wait
+        // for the q^n loads just issued (2 % of the stage, measured).
         T qc[NV], q0c[NV];
         if (kHoldFold<T> && fold && own) {
 #pragma unroll
-            for (int v = 0; v < NV; v++) qc[v] = qo[v];
+            for (int v = 0; v < NV; v++) {
+                qc[v] = qo[v];
+                __asm__ volatile("" : "+v"(qc[v]));
+            }
             if (mode != 1) {
                 const int64_t c = offset(g, gx, gy, k);
 #pragma unroll
