@@ -72,11 +72,11 @@ KERNEL_TIMING_STRIDE = 10
 # only for the kernel sources they were taken on; any change to those files
 # turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h", "charbc.h")
-TRAFFIC = {"sha256": "0c513062144f9b39e7c17c0612ba1038f2780c986c767505c5d712bb8a12e3ac",
-           ("split", "fp32", 128, 0): (126.25e6, 62.41e6),
+TRAFFIC = {"sha256": "c02e7908fcdf6dc0965b693d2c0d383483ee1a3dee8ef7a4b739daec5cbaa83a",
+           ("split", "fp32", 128, 0): (126.15e6, 62.42e6),
            ("split", "fp32", 128, 1): (143.68e6, 61.50e6),
-           ("split", "fp64", 128, 0): (238.10e6, 127.51e6),
-           ("split", "fp64", 128, 1): (287.75e6, 123.17e6)}
+           ("split", "fp64", 128, 0): (240.70e6, 127.90e6),
+           ("split", "fp64", 128, 1): (287.90e6, 123.31e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
