@@ -215,10 +215,11 @@ int mfc_max_wavespeed(mfc_grid *g, const void *q, double *smax_host, void *strea
 int mfc_rk3_step(mfc_grid *g, void *q, double cfl, double dt, double *dt_used_dev, void *stream);
 
 /* nsteps SSP-RK3 steps as by mfc_rk3_step (dt_used_dev NULL), enqueued back
- * to back.  MFC_KERNEL_SPLIT with cfl > 0 and no characteristic face: the
- * z pass of each step's last stage also reduces the wave speeds of the
- * state it writes (the next step's q^n), so the next step's size is set
- * before its first stage, whose x+y pass then forms its part of the stage
+ * to back.  MFC_KERNEL_SPLIT with cfl > 0: the z pass of each step's last
+ * stage also reduces the wave speeds of the state it writes (the next step's
+ * q^n; with characteristic z faces, the boundary pass reduces those faces'
+ * cells after it has changed them), so the next step's size is set before
+ * its first stage, whose x+y pass then forms its part of the stage
  * combination (q + dt L_xy, the z pass adding dt L_z) instead of the z pass
  * reading q^n again.  The step sizes are those of single mfc_rk3_step calls
  * on the same states, bit for bit; the states agree to rounding. */

@@ -134,16 +134,40 @@ __device__ __forceinline__ bool face_delta(const Grid &g, int c[3], const T *__r
 // it).  A cell on several characteristic faces (an edge or corner) belongs
 // to the first of them, whose lanes add the changes of all of them in face
 // order: every cell is written by one lane, once, in a fixed order.
+// smax_partial (the split path's last stage of a step followed by another of
+// the same run): the pass also reduces max_d (|u_d| + c) of the cells it
+// writes, as the z kernel does for the others, one maximum per workgroup.
+template <int NDIM, class T, int ORDER, bool STORED>
+__device__ __forceinline__ double cbc_cell(const Grid &g, const CbcFaces &F, const T *__restrict__ q, T *out, int mode,
+                                           double dt, const double *__restrict__ dt_dev, bool reduce, int64_t gt,
+                                           bool &bad);
+
 template <int NDIM, class T, int ORDER, bool STORED>
 __global__ void __launch_bounds__(kCbcThreads, MFC_CBC_WAVES)
     k_cbc(Grid g, CbcFaces F, const T *__restrict__ q, T *out, int mode, double dt, const double *__restrict__ dt_dev,
-          int *__restrict__ flag)
+          int *__restrict__ flag, double *__restrict__ smax_partial)
+{
+    bool bad = false;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double smax = cbc_cell<NDIM, T, ORDER, STORED>(g, F, q, out, mode, dt, dt_dev, smax_partial != nullptr, gt, bad);
+    if (smax_partial) {   // every lane of the workgroup (one wavefront) takes part
+        static_assert(kCbcThreads == 64, "one wavefront per workgroup");
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) smax = __builtin_fmax(smax, __shfl_xor(smax, o, 64));
+        if (threadIdx.x == 0) smax_partial[blockIdx.x] = smax;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+template <int NDIM, class T, int ORDER, bool STORED>
+__device__ __forceinline__ double cbc_cell(const Grid &g, const CbcFaces &F, const T *__restrict__ q, T *out, int mode,
+                                           double dt, const double *__restrict__ dt_dev, bool reduce, int64_t gt,
+                                           bool &bad)
 {
     constexpr int NV = 4 + NDIM;
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t t = STORED ? gt : gt >> 1;   // the cell; both lanes of a pair leave or stay together
     const int half = STORED ? 1 : (int)(gt & 1);
-    if (t >= F.start[6]) return;
+    if (t >= F.start[6]) return 0.0;
     int my = -1;
     int64_t first = 0;
 #pragma unroll
@@ -152,7 +176,7 @@ __global__ void __launch_bounds__(kCbcThreads, MFC_CBC_WAVES)
             my = f;
             first = F.start[f];
         }
-    if (my < 0) return;
+    if (my < 0) return 0.0;
     const int D = my >> 1;
     const int nD = D == 0 ? g.n[0] : (D == 1 ? g.n[1] : g.n[2]);
     const int b = (my & 1) ? nD - 1 : 0;
@@ -167,12 +191,11 @@ __global__ void __launch_bounds__(kCbcThreads, MFC_CBC_WAVES)
 #pragma unroll
     for (int f = 0; f < 2 * NDIM; f++)
         if (((F.mask >> f) & 1) && c[f >> 1] == ((f & 1) ? g.n[f >> 1] - 1 : 0)) on |= 1 << f;
-    if (on & ((1 << my) - 1)) return;   // an earlier face owns this cell
+    if (on & ((1 << my) - 1)) return 0.0;   // an earlier face owns this cell
 
     T delta[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) delta[v] = T(0);
-    bool bad = false;
     if (on & 1) bad |= face_delta<NDIM, 0, 0, T, ORDER, STORED>(g, c, q, delta, half);
     if (on & 2) bad |= face_delta<NDIM, 0, 1, T, ORDER, STORED>(g, c, q, delta, half);
     if constexpr (NDIM >= 2) {
@@ -187,15 +210,33 @@ __global__ void __launch_bounds__(kCbcThreads, MFC_CBC_WAVES)
     const int64_t off = (int64_t)(c[2] + g.off[2]) * g.stride[2] + (int64_t)(c[1] + g.off[1]) * g.stride[1] +
                         (c[0] + g.off[0]);
     const T w_dt = mode == 0 ? T(1) : T((mode == 1 ? 1.0 : (mode == 2 ? 0.25 : 2.0 / 3.0)) * (dt_dev ? *dt_dev : dt));
+    double smax = 0.0;
     if (half) {
+        T r[NV];
 #pragma unroll
-        for (int v = 0; v < NV; v++) out[v * g.vstride + off] += w_dt * delta[v];
+        for (int v = 0; v < NV; v++) {
+            r[v] = out[v * g.vstride + off] + w_dt * delta[v];
+            out[v * g.vstride + off] = r[v];
+        }
+        if (reduce) {   // as the x+y pass of a first stage forms it from the stored values
+            T w[NV];
+            cons_to_prim<NDIM, T>(g, r, w);
+            double Gam, Pi;
+            mixture<double>(g, double(w[NV - 1]), Gam, Pi);
+            const double cs = sqrtT(sound2<double>(Gam, Pi, double(w[0]) + double(w[1]), double(w[NV - 2])));
+#pragma unroll
+            for (int d = 0; d < NDIM; d++) {
+                const double a = __builtin_fabs(double(w[2 + d])) + cs;
+                smax = __builtin_fmax(smax, g.stretched ? a * inv_width(g, d, c[d]) : a);
+            }
+        }
     }
-    if (bad) atomicOr(flag, 1);
+    return smax;
 }
 
 template <class T, int ORDER>
-void launch_t(mfc_grid *h, const void *q, void *out, int mode, double dt, const double *dt_dev, hipStream_t s)
+void launch_t(mfc_grid *h, const void *q, void *out, int mode, double dt, const double *dt_dev, hipStream_t s,
+              double *smax_partial)
 {
     const Grid &g = h->g;
     CbcFaces F{};
@@ -221,23 +262,31 @@ void launch_t(mfc_grid *h, const void *q, void *out, int mode, double dt, const 
     switch (g.ndim) {
     case 1:
         hipLaunchKernelGGL((k_cbc<1, T, ORDER, false>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev,
-                           h->flag);
+                           h->flag, nullptr);
         break;
     case 2:
         hipLaunchKernelGGL((k_cbc<2, T, ORDER, false>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt, dt_dev,
-                           h->flag);
+                           h->flag, nullptr);
         break;
     default:
         if (stored)
             hipLaunchKernelGGL((k_cbc<3, T, ORDER, true>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt,
-                               dt_dev, h->flag);
+                               dt_dev, h->flag, smax_partial);
         else
             hipLaunchKernelGGL((k_cbc<3, T, ORDER, false>), grid, dim3(kCbcThreads), 0, s, g, F, a, o, mode, dt,
-                               dt_dev, h->flag);
+                               dt_dev, h->flag, nullptr);
     }
 }
 
 }  // namespace
+
+int64_t cbc_stored_blocks(const Grid &g)
+{
+    int64_t total = 0;
+    for (int f = 4; f < 6; f++)
+        if (g.ndim == 3 && g.bc[f] == MFC_BC_CHARACTERISTIC) total += (int64_t)g.n[0] * g.n[1];
+    return (total + kCbcThreads - 1) / kCbcThreads;
+}
 
 bool has_cbc(const mfc_grid *h)
 {
@@ -246,18 +295,20 @@ bool has_cbc(const mfc_grid *h)
     return false;
 }
 
-int launch_cbc(mfc_grid *h, const void *q, void *out, int mode, double dt, const double *dt_dev, hipStream_t s)
+int launch_cbc(mfc_grid *h, const void *q, void *out, int mode, double dt, const double *dt_dev, hipStream_t s,
+               double *smax_partial)
 {
     const bool f32 = h->desc.precision == MFC_FP32_MIXED;
+    double *sp = smax_partial;
     switch (h->g.order) {
     case 3:
-        f32 ? launch_t<float, 3>(h, q, out, mode, dt, dt_dev, s) : launch_t<double, 3>(h, q, out, mode, dt, dt_dev, s);
+        f32 ? launch_t<float, 3>(h, q, out, mode, dt, dt_dev, s, sp) : launch_t<double, 3>(h, q, out, mode, dt, dt_dev, s, sp);
         break;
     case 1:
-        f32 ? launch_t<float, 1>(h, q, out, mode, dt, dt_dev, s) : launch_t<double, 1>(h, q, out, mode, dt, dt_dev, s);
+        f32 ? launch_t<float, 1>(h, q, out, mode, dt, dt_dev, s, sp) : launch_t<double, 1>(h, q, out, mode, dt, dt_dev, s, sp);
         break;
     default:
-        f32 ? launch_t<float, 5>(h, q, out, mode, dt, dt_dev, s) : launch_t<double, 5>(h, q, out, mode, dt, dt_dev, s);
+        f32 ? launch_t<float, 5>(h, q, out, mode, dt, dt_dev, s, sp) : launch_t<double, 5>(h, q, out, mode, dt, dt_dev, s, sp);
     }
     return hip_status(hipGetLastError(), "characteristic boundary launch");
 }

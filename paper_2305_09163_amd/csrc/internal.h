@@ -69,8 +69,14 @@ int build_stretch_tables(mfc_grid *h, const mfc_grid_desc *d);
 // Characteristic boundaries (cbc.hip): whether a face has one, and the
 // post-pass that replaces the boundary cells' normal terms in `out` (the
 // right-hand side for mode 0, else the stage result of that mode).
+// smax_partial non-null (the split path's last stage of a step followed by
+// another of the same run): the pass also writes the wave-speed maxima of the
+// cells it changes, cbc_stored_blocks(g) of them.
 bool has_cbc(const mfc_grid *h);
-int launch_cbc(mfc_grid *h, const void *q, void *out, int mode, double dt, const double *dt_dev, hipStream_t s);
+int launch_cbc(mfc_grid *h, const void *q, void *out, int mode, double dt, const double *dt_dev, hipStream_t s,
+               double *smax_partial = nullptr);
+// Workgroups of the split path's boundary pass (the z faces' cells).
+int64_t cbc_stored_blocks(const Grid &g);
 void free_stretch_tables(mfc_grid *h);
 int hip_status(hipError_t e, const char *what);
 

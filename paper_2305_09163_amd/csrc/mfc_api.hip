@@ -377,7 +377,11 @@ int rhs_dispatch(mfc_grid *h, const void *q, const void *q0, void *out, int mode
     if (h->desc.kernel == MFC_KERNEL_STAGED) st = launch_rhs_staged(h, q, q0, out, mode, dt, dt_dev, s);
     else if (h->desc.kernel == MFC_KERNEL_SPLIT) st = launch_rhs_split(h, q, q0, out, mode, dt, dt_dev, s, cfl, zmax);
     else st = launch_rhs_fused(h, q, q0, out, mode, dt, dt_dev, s);
-    if (st == MFC_OK && has_cbc(h)) st = launch_cbc(h, q, out, mode, dt, dt_dev, s);
+    // with characteristic faces, a wave-speed-reducing last stage leaves the
+    // z faces' cells to the boundary pass, whose maxima follow the z kernel's
+    if (st == MFC_OK && has_cbc(h))
+        st = launch_cbc(h, q, out, mode, dt, dt_dev, s,
+                        zmax ? zmax + split_z_partials(h->g, h->desc.precision == MFC_FP32_MIXED) : nullptr);
     return st;
 }
 
@@ -534,7 +538,8 @@ int mfc_init_grid(const mfc_grid_desc *desc, mfc_grid **out)
         g.cbc_fv = h->cbc_fv;
     }
     h->partial_len = std::max<int64_t>(
-        kReduceBlocks, desc->ndim == 3 ? std::max(split_xy_blocks(g), split_z_partials(g, is_fp32(h))) : 0);
+        kReduceBlocks,
+        desc->ndim == 3 ? std::max(split_xy_blocks(g), split_z_partials(g, is_fp32(h)) + cbc_stored_blocks(g)) : 0);
     alloc((void **)&h->partial, h->partial_len * 8);
     alloc((void **)&h->scalars, 4 * 8);
     alloc((void **)&h->flag, 8);
@@ -653,12 +658,18 @@ namespace {
 // reduce the wave speeds of q^{n+1} as it writes it (the x+y pass of the
 // next step's first stage would reduce the same values to the same
 // maxima), so that the next step's size is known before its first stage and
-// that stage's x+y pass forms its part of the combination.  Not with
-// characteristic faces, whose boundary pass changes boundary cells after the
-// z pass.
+// that stage's x+y pass forms its part of the combination.  With
+// characteristic faces the boundary pass, which changes the z faces' cells
+// after the z pass, reduces those cells itself.
 bool carries_wavespeed(const mfc_grid *h, double cfl)
 {
-    return cfl > 0.0 && h->desc.kernel == MFC_KERNEL_SPLIT && !has_cbc(h);
+    return cfl > 0.0 && h->desc.kernel == MFC_KERNEL_SPLIT;
+}
+
+// Number of wave-speed maxima a carrying last stage leaves in h->partial.
+int64_t carried_partials(const mfc_grid *h)
+{
+    return split_z_partials(h->g, is_fp32(h)) + (has_cbc(h) ? cbc_stored_blocks(h->g) : 0);
 }
 
 // One SSP-RK3 step.  carried_in: the wave-speed partials of q^n are in
@@ -688,7 +699,7 @@ int rk3_step_launches(mfc_grid *h, void *q, double cfl, double dt, double *dt_us
     const bool fill = h->desc.kernel != MFC_KERNEL_SPLIT;
     if (fill && (st = fill_ghosts(h, q, s))) return st;
     if (carried_in) {
-        launch_step_begin(h, h->partial, (int)split_z_partials(h->g, is_fp32(h)), cfl, 0.0, s);
+        launch_step_begin(h, h->partial, (int)carried_partials(h), cfl, 0.0, s);
         if ((st = rhs_dispatch(h, q, q, A, 1, 0.0, dt_dev, s))) return st;
     } else if (h->desc.kernel == MFC_KERNEL_SPLIT && cfl > 0.0) {
         // the x+y pass of the first stage reduces the wave speeds of q^n and

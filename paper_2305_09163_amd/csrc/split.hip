@@ -776,7 +776,11 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
                         r[v] = lx[v] + sz * L[v];
                         out[v * g.vstride + c] = r[v];
                     }
-                    if constexpr (SMAX) {   // |u_d| + c of the stored state (non-uniform cells: over dx_d)
+                    // |u_d| + c of the stored state (non-uniform cells: over dx_d);
+                    // the cells of characteristic z faces are left to the
+                    // boundary pass, which changes them after this kernel
+                    const bool zface = KEEP && ((k == 0 && (g.cbc_mask & 16)) || (k == g.n[2] - 1 && (g.cbc_mask & 32)));
+                    if (SMAX && !zface) {
                         T w[NV];
                         cons_to_prim<3, T>(g, r, w);
                         double Gam, Pi;
@@ -844,12 +848,10 @@ int rhs_split(mfc_grid *h, const T *q, const T *q0, T *out, int mode, double dt,
     if (partial) launch_step_begin(h, partial, (int)split_xy_blocks(g), cfl, 0.0, s);
     timing_begin(h, s, 1);
     bool done = false;
-    if constexpr (!KEEP) {   // characteristic faces never carry the wave speeds (the boundary pass follows)
-        if (zmax && mode != 0 && fold) {
-            hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH, KEEP, false, true>), gz, dim3(kZX * kZY), 0, s, g, q,
-                               out, lxy, mode, dt, dt_dev, h->flag, h->mlp, h->logit_tau, se, zmax);
-            done = true;
-        }
+    if (zmax && mode != 0 && fold) {
+        hipLaunchKernelGGL((k_z<T, ROUTE, ORDER, STRETCH, KEEP, false, true>), gz, dim3(kZX * kZY), 0, s, g, q, out,
+                           lxy, mode, dt, dt_dev, h->flag, h->mlp, h->logit_tau, se, zmax);
+        done = true;
     }
     if (done) {
     } else if (mode != 0 && !fold) {
