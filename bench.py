@@ -72,11 +72,11 @@ KERNEL_TIMING_STRIDE = 10
 # only for the kernel sources they were taken on; any change to those files
 # turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h", "charbc.h")
-TRAFFIC = {"sha256": "da022ed384ec41473be5941f50ae071ad1c3f153d9179005edfa64ffbc4e9bc6",
-           ("split", "fp32", 128, 0): (126.15e6, 62.42e6),
-           ("split", "fp32", 128, 1): (143.68e6, 61.50e6),
-           ("split", "fp64", 128, 0): (240.70e6, 127.90e6),
-           ("split", "fp64", 128, 1): (287.90e6, 123.31e6)}
+TRAFFIC = {"sha256": "8c755235899f5ff5995c53b0c00d063c64887c17773428c0695b7e212da6d8d6",
+           ("split", "fp32", 128, 0): (126.18e6, 62.45e6),
+           ("split", "fp32", 128, 1): (143.65e6, 61.50e6),
+           ("split", "fp64", 128, 0): (241.77e6, 128.02e6),
+           ("split", "fp64", 128, 1): (288.31e6, 123.56e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12

@@ -571,7 +571,7 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH, KEEP>))
 #define MFC_Z_RING 4
 #endif
 #ifndef MFC_Z_EARLY64
-#define MFC_Z_EARLY64 0
+#define MFC_Z_EARLY64 1
 #endif
 #ifndef MFC_Z_EARLY32
 #define MFC_Z_EARLY32 1
@@ -586,8 +586,10 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH, KEEP>))
 
 template <class T>
 constexpr int kZWaves = sizeof(T) == 8 ? MFC_Z_WAVES64 : MFC_Z_WAVES32;
-template <class T>
-constexpr bool kZEarly = sizeof(T) == 8 ? MFC_Z_EARLY64 : MFC_Z_EARLY32;
+// FP64 with characteristic faces loads them late: its z-face terms leave
+// no registers for them (15 spilled otherwise)
+template <class T, bool KEEP>
+constexpr bool kZEarly = sizeof(T) == 8 ? (MFC_Z_EARLY64 && !KEEP) : MFC_Z_EARLY32;
 // the routed variant keeps LDS for the network and its feature exchange
 template <bool ROUTE>
 constexpr int kRing = ROUTE ? MFC_Z_RING_ROUTE : MFC_Z_RING;
@@ -685,9 +687,10 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
         for (int st = 0; st < steps; st++) {
             const int k = kfirst + S * st;
             bad |= load_prim_z<T>(g, q, gx, gy, k + H * S, zr[kZReg - 1]);
-            // FP32: the operands of the stage update of cell k are loaded before
-            // the reconstruction so that their latency overlaps it (the FP64
-            // kernel has no registers to spare for them and loads them late)
+            // the operands of the stage update of cell k are loaded before the
+            // reconstruction so that their latency overlaps it (FP64: 3-5 us
+            // per launch faster measured, although the wave-speed-reducing
+            // variant then spills a few registers)
             T lx[NV], qb[NV];
             auto load_update = [&](int64_t c) {
 #pragma unroll
@@ -698,7 +701,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
                 }
             };
             const bool upd = st >= 2 && own;   // cell k is in the chunk
-            if constexpr (kZEarly<T>) {
+            if constexpr (kZEarly<T, KEEP>) {
                 if (upd) load_update(offset(g, gx, gy, k));
             }
             T pn[NV], mn[NV], Fzn[NV + 1];
@@ -759,9 +762,9 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
                     if (k == 0 && (g.cbc_mask & 16)) store_normal_terms<4, T>(g, gx, g.n[0], gy, Lz, dz);
                     if (k == g.n[2] - 1 && (g.cbc_mask & 32)) store_normal_terms<5, T>(g, gx, g.n[0], gy, Lz, dz);
                 }
-                // every operand before the first store (the FP64 kernel loads
-                // them here, having no registers to spare earlier)
-                if constexpr (!kZEarly<T>) load_update(c);
+                // every operand before the first store (here when they are
+                // not loaded early)
+                if constexpr (!kZEarly<T, KEEP>) load_update(c);
 #pragma unroll
                 for (int v = 0; v < NV; v++) L[v] = (Flo[v] - Fhi[v]) * idz;
                 divu = (Fhi[NV] - Flo[NV]) * idz;
