@@ -220,9 +220,10 @@ constexpr int kXYWaves = ROUTE ? 2
                                           : (sizeof(T) == 8 ? 3 : (KEEP ? 4 : MFC_XY_WAVES32)));
 
 // The x+y pass holds the operands of its part of the stage combination in
-// registers from the start of each plane (FP64: their latency then overlaps
-// the plane's work, measured faster), or loads them at its end (FP32, whose
-// five wavefronts per SIMD leave no registers for them).
+// registers from the start (the stage input) and the middle (q^n) of each
+// plane (FP64: their latency then overlaps the plane's work, measured
+// faster), or loads them at its end (FP32, whose five wavefronts per SIMD
+// leave no registers for them).
 #ifndef MFC_XY_HOLD64
 #define MFC_XY_HOLD64 1
 #endif
@@ -353,23 +354,20 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH, KEEP>))
             }
         }
         __syncthreads();
-        // operands of the x+y part of the stage combination, held from here
-        // to the end of the plane so that the q^n load overlaps its work:
-        // the cell's stage input (before the next plane's fetch replaces it)
-        // and q^n.  The copy is kept ahead of the q^n loads (the empty asm):
-        // placed after them, its wait for the fetched values was also a wait
-        // for the q^n loads just issued (2 % of the stage, measured).
+        // operands of the x+y part of the stage combination, held in
+        // registers to the end of the plane: the cell's stage input, copied
+        // here before the next plane's fetch replaces it, and q^n, loaded
+        // after the x sweep (below) so that its latency overlaps the y sweep
+        // and its traffic does not coincide with the fetch (issued with the
+        // fetch, stages 2 and 3 took 5-7 us more).  The copy is kept ahead
+        // of the loads that follow it (the empty asm): placed after them, its
+        // wait for the fetched values was also a wait for those loads.
         T qc[NV], q0c[NV];
         if (kHoldFold<T> && fold && own) {
 #pragma unroll
             for (int v = 0; v < NV; v++) {
                 qc[v] = qo[v];
                 __asm__ volatile("" : "+v"(qc[v]));
-            }
-            if (mode != 1) {
-                const int64_t c = offset(g, gx, gy, k);
-#pragma unroll
-                for (int v = 0; v < NV; v++) q0c[v] = ld_once(&q0[v * g.vstride + c]);
             }
         }
         if (k + 1 < z1) fetch(k + 1);
@@ -438,6 +436,11 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH, KEEP>))
         }
         // ---- y: thread p reconstructs row p / TX - 1 of column p % TX and
         // solves the face on its + side
+        if (kHoldFold<T> && fold && own && mode != 1) {   // q^n of the combination (see above)
+            const int64_t c = offset(g, gx, gy, k);
+#pragma unroll
+            for (int v = 0; v < NV; v++) q0c[v] = ld_once(&q0[v * g.vstride + c]);
+        }
         if constexpr (ROUTE && R::in_flux) __syncthreads();  // the x fluxes above are read before the area is reused
         {
             const int p = tid;
