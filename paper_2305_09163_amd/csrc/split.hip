@@ -219,11 +219,10 @@ constexpr int kXYWaves = ROUTE ? 2
                                : (STRETCH ? (sizeof(T) == 8 ? 2 : 4)
                                           : (sizeof(T) == 8 ? 3 : (KEEP ? 4 : MFC_XY_WAVES32)));
 
-// The x+y pass holds the operands of its part of the stage combination in
-// registers from the start (the stage input) and the middle (q^n) of each
-// plane (FP64: their latency then overlaps the plane's work, measured
-// faster), or loads them at its end (FP32, whose five wavefronts per SIMD
-// leave no registers for them).
+// The x+y pass holds the stage input of its part of the stage combination
+// in registers from the start of each plane and loads q^n late in it
+// (FP64, measured faster), or loads both at its end (FP32, whose five
+// wavefronts per SIMD leave no registers for them).
 #ifndef MFC_XY_HOLD64
 #define MFC_XY_HOLD64 1
 #endif
@@ -354,14 +353,16 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH, KEEP>))
             }
         }
         __syncthreads();
-        // operands of the x+y part of the stage combination, held in
-        // registers to the end of the plane: the cell's stage input, copied
-        // here before the next plane's fetch replaces it, and q^n, loaded
-        // after the x sweep (below) so that its latency overlaps the y sweep
-        // and its traffic does not coincide with the fetch (issued with the
-        // fetch, stages 2 and 3 took 5-7 us more).  The copy is kept ahead
-        // of the loads that follow it (the empty asm): placed after them, its
-        // wait for the fetched values was also a wait for those loads.
+        // operands of the x+y part of the stage combination: the cell's
+        // stage input, copied here before the next plane's fetch replaces it
+        // and held in registers to the end of the plane, and q^n, loaded
+        // late in the plane (written after the x sweep below; the compiler
+        // issues the loads after the last barrier, shortly before their use)
+        // so that its traffic does not coincide with the fetch (issued with
+        // the fetch, stages 2 and 3 took 5-7 us more).  The copy is kept
+        // ahead of the loads that follow it (the empty asm): placed after
+        // them, its wait for the fetched values was also a wait for those
+        // loads.
         T qc[NV], q0c[NV];
         if (kHoldFold<T> && fold && own) {
 #pragma unroll
