@@ -590,10 +590,11 @@ __global__ void __launch_bounds__(NT, (kXYWaves<T, ROUTE, STRETCH, KEEP>))
 
 template <class T>
 constexpr int kZWaves = sizeof(T) == 8 ? MFC_Z_WAVES64 : MFC_Z_WAVES32;
-// FP64 with characteristic faces loads them late: its z-face terms leave
-// no registers for them (15 spilled otherwise)
-template <class T, bool KEEP>
-constexpr bool kZEarly = sizeof(T) == 8 ? (MFC_Z_EARLY64 && !KEEP) : MFC_Z_EARLY32;
+// FP64 with characteristic faces, and the FP64 variant that re-reads its
+// stage input, load them late: the z-face terms or the second stage-input
+// read leave no registers for them (15 and 20 spilled otherwise)
+template <class T, bool KEEP, bool REREAD>
+constexpr bool kZEarly = sizeof(T) == 8 ? (MFC_Z_EARLY64 && !KEEP && !REREAD) : MFC_Z_EARLY32;
 // the routed variant keeps LDS for the network and its feature exchange
 template <bool ROUTE>
 constexpr int kRing = ROUTE ? MFC_Z_RING_ROUTE : MFC_Z_RING;
@@ -705,7 +706,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
                 }
             };
             const bool upd = st >= 2 && own;   // cell k is in the chunk
-            if constexpr (kZEarly<T, KEEP>) {
+            if constexpr (kZEarly<T, KEEP, REREAD>) {
                 if (upd) load_update(offset(g, gx, gy, k));
             }
             T pn[NV], mn[NV], Fzn[NV + 1];
@@ -768,7 +769,7 @@ __global__ void __launch_bounds__(kZX * kZY, kZWaves<T>)
                 }
                 // every operand before the first store (here when they are
                 // not loaded early)
-                if constexpr (!kZEarly<T, KEEP>) load_update(c);
+                if constexpr (!kZEarly<T, KEEP, REREAD>) load_update(c);
 #pragma unroll
                 for (int v = 0; v < NV; v++) L[v] = (Flo[v] - Fhi[v]) * idz;
                 divu = (Fhi[NV] - Flo[NV]) * idz;
