@@ -73,10 +73,10 @@ KERNEL_TIMING_STRIDE = 10
 # turns `traffic` back to null.
 TRAFFIC_SOURCES = ("split.hip", "physics.h", "internal.h", "charbc.h")
 TRAFFIC = {"sha256": "bcb207b46f1a439ca8171579f25553c3850d1683b220d2d12bbe837ebbe5d77d",
-           ("split", "fp32", 128, 0): (126.13e6, 62.42e6),
+           ("split", "fp32", 128, 0): (126.15e6, 62.40e6),
            ("split", "fp32", 128, 1): (143.65e6, 61.50e6),
-           ("split", "fp64", 128, 0): (243.45e6, 127.62e6),
-           ("split", "fp64", 128, 1): (288.18e6, 123.54e6)}
+           ("split", "fp64", 128, 0): (242.79e6, 127.68e6),
+           ("split", "fp64", 128, 1): (288.31e6, 123.55e6)}
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
