@@ -45,7 +45,7 @@ def build(force: bool = True) -> str:
               (_LIB_FMA_PATH, ["-ffp-contract=fast", "-mfma"]))
     for path, extra in builds:
         if force or not os.path.exists(path):
-            tmp = path + ".tmp"
+            tmp = "%s.%d.tmp" % (path, os.getpid())   # parallel test workers may build at once
             subprocess.run(["gcc", "-O2", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
                             *extra, "-o", tmp, _SRC, "-lm"], check=True)
             os.replace(tmp, path)
